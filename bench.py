@@ -1,0 +1,160 @@
+"""Throughput of the canonical-ensemble DQMC hot path on one MI355X.
+
+Workload: the dilute Fermi gas, 32x32 periodic Hubbard lattice (N = 1024),
+t = 1, U = 4, 8 up + 8 down particles, beta = 16, dtau = 0.05 (320 slices),
+QR every 10 slices, all FP64, 64 independent walkers (seeds 1..64) advanced
+together (one workgroup per walker).  A step is one full sweep of every
+walker: left-stack build, forward pass with N * L_tau Ising-flip attempts and
+QR stabilisation, and N_sigma particle-hole swaps per spin.
+
+Prints one JSON line.  value = HS-field updates per second (flip attempts of
+all walkers / wall time of the timed sweeps, inputs already resident).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_WALKERS = 64
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_forward(N, ne_up, ne_dn, L, nstab):
+    """Algorithmic HBM bytes of one forward-pass launch for one walker (FP64).
+
+    Per slice each spin streams Phi_R and Phi_L (N x Ne) in and out once
+    (diagonal factor, flips and checkerboard applied while resident):
+    2 sides * 2 (read + write) * N * Ne * 8.  Per stabilisation block the QR
+    reads Phi twice and writes Q twice and the fresh Phi_L is read once:
+    5 * N * Ne * 8.  Fields: one read and one write byte per site and slice.
+    """
+    per_spin_slice = lambda ne: 4 * N * ne * 8
+    per_spin_block = lambda ne: 5 * N * ne * 8
+    nblk = (L + nstab - 1) // nstab
+    b = 0
+    for ne in (ne_up, ne_dn):
+        b += L * per_spin_slice(ne) + nblk * per_spin_block(ne)
+    b += 2 * L * N
+    return b
+
+
+def _oracle_worker(args):
+    seed, sweeps = args
+    import oracle
+    from paper_2601_08552_amd import workloads as W
+    lat, par = W.config_dilute(seed=seed, walker_id=seed - 1)
+    w = oracle.Walker(lat, par)
+    t0 = time.perf_counter()
+    w.sweep(sweeps)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(procs, sweeps):
+    """The FP64 oracle, unmodified, one walker per process on the host cores."""
+    from paper_2601_08552_amd import workloads as W
+    lat, par = W.config_dilute()
+    ctxm = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctxm.Pool(procs) as pool:
+        times = pool.map(_oracle_worker, [(s + 1, sweeps) for s in range(procs)])
+    wall = time.perf_counter() - t0
+    upd = procs * sweeps * lat.n_sites * par.L_tau
+    return {"value": upd / max(times), "unit": "HS-field updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} walkers x {sweeps} sweep(s) of the 32x32 dilute workload, one process per core "
+                      f"(rate = updates / slowest process time; pool wall {wall:.1f} s)",
+            "sec_per_sweep_per_core": float(np.median(times) / sweeps)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--walkers", type=int, default=N_WALKERS)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=0)
+    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2601_08552_amd import lecqmc
+    from paper_2601_08552_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = lecqmc.Context(0, stream=stream)
+    walkers = []
+    for s in range(args.walkers):
+        lat, par = W.config_dilute(seed=s + 1, walker_id=s)
+        walkers.append(lecqmc.Walker(ctx, lat, par))
+    N, L = lat.n_sites, par.L_tau
+    for _ in range(args.warmup):
+        lecqmc.sweep_batch(walkers, 1)
+    ctx.synchronize()
+    ctx.set_timing(True)
+    ctx.phase_times()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        lecqmc.sweep_batch(walkers, 1)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_phase, cnt = ctx.phase_times()
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    updates = args.walkers * N * L * args.steps
+    value = updates / wall
+    fwd_ms = ms_phase[1] / max(cnt[1], 1)
+    alg = algorithmic_bytes_forward(N, par.n_up, par.n_dn, L, par.n_stab) * args.walkers
+    achieved = alg / (fwd_ms * 1e-3) / 1e9
+    st = walkers[0].stats()
+    out = {
+        "metric": "HS-field updates/s per GPU at stated err vs FP64 oracle; p50/p99 sweep latency",
+        "value": value,
+        "unit": "HS-field updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dilute Fermi gas 32x32 Hubbard, U=4, 8+8 particles, beta=16, dtau=0.05, "
+                               "QR every 10 slices, FP64", "walkers": args.walkers, "N": N, "L_tau": L,
+                   "ne_per_spin": par.n_up},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "note": "per-walker sweep latency = batched step time (all walkers advance together)"},
+        "phase_ms_per_launch": {"left_stack": ms_phase[0] / max(cnt[0], 1), "forward": fwd_ms,
+                                "fock": ms_phase[2] / max(cnt[2], 1)},
+        "accuracy": {"vs_oracle": "bit-identical Markov chain; log-weight, Green's function and ratios "
+                                  "within 1e-10 relative (parity tests)",
+                     "logw_drift": st["logw_drift"], "max_wrap_err": st["max_wrap_err"]},
+        "roofline": {"bound": "hbm", "kernel": "k_forward", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg},
+    }
+    if not args.no_cpu_baseline:
+        procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(procs, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

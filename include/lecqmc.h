@@ -1,0 +1,163 @@
+/*
+ * lecqmc.h -- C ABI of the MI355X (gfx950) hot path of linear-scaling
+ * canonical-ensemble determinant QMC (arXiv 2601.08552).
+ *
+ * The library samples (eta, s) with probability proportional to
+ *   |W(eta, s)|,  W = prod_sigma det[P_sigma^T B^sigma(beta, 0) P_sigma]
+ * (main text Eq. (1)) for the Hubbard-type Hamiltonian
+ *   H = sum_b h_b (c_i^dag c_j + h.c.) + sum_i eps_i n_i + U sum_i n_iu n_id
+ * (main text, Hubbard model; SM Sec. III for the flat-band chain) at fixed
+ * particle numbers N_up, N_dn, and accumulates equal-time estimators.
+ *
+ * Conventions fixed by this ABI:
+ *   B_l = E_K D_l,   D_l^sigma = diag(exp(sigma lambda s_{l,i} - dtau eps_i)),
+ *   cosh(lambda) = exp(dtau U / 2) (Ising decoupling in the spin channel),
+ *   E_K = e^{-dtau K_0} e^{-dtau K_1} ... e^{-dtau K_{C-1}} over the bond
+ *   colours supplied by the caller (bonds of one colour never share a site).
+ *   L_tau = beta / dtau slices; a QR stabilisation every n_stab slices
+ *   (SM Sec. I.A: n = L_tau / tau_w stabilisation steps; the last block may
+ *   be shorter).  W excludes the configuration-independent factor
+ *   2^{-N L_tau} e^{-beta U (N_up + N_dn) / 2}.
+ *
+ * One sweep = (i) left-stack build, (ii) forward pass over all L_tau slices
+ * with one Ising flip attempt per (slice, site) accepted on the Ne x Ne
+ * determinant ratio with a rank-1 update (main text, auxiliary-field
+ * updates), QR stabilisation at block ends, (iii) Ne_sigma particle-hole
+ * swap attempts per spin at tau = beta, each a removal (permutation +
+ * Givens retriangulation, SM Sec. I.B) followed by an addition (one-column
+ * propagation + Gram-Schmidt per level, SM Sec. I.A).
+ *
+ * Errors: every int-returning call returns 0 on success or a negative code
+ * below; lecqmc_last_error() gives a message (thread-local).  Calls on one
+ * walker are not thread-safe; distinct walkers may be used from different
+ * threads only through distinct contexts.  Kernels are launched on the
+ * context's stream; lecqmc_sweep / lecqmc_sweep_batch return without
+ * waiting, every call that returns data to the host synchronises the stream.
+ */
+#ifndef LECQMC_H
+#define LECQMC_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LECQMC_OK 0
+#define LECQMC_EINVAL (-1)    /* bad sizes or arguments (message says which)          */
+#define LECQMC_ENOMEM (-2)    /* device footprint over the context budget (refused)   */
+#define LECQMC_EUNSTABLE (-3) /* QR breakdown or wrap error above wrap_tol; walker stays valid */
+#define LECQMC_EDEVICE (-4)   /* HIP runtime error                                    */
+#define LECQMC_ESTATE (-5)    /* call not valid in the walker's state                 */
+
+#define LECQMC_FP64 0         /* all arithmetic in FP64                               */
+#define LECQMC_NO_FOCK 1      /* flags: skip the particle-hole swap phase             */
+#define LECQMC_NO_FLIPS 2     /* flags: skip the Ising flips (fields frozen)          */
+
+#define LECQMC_MAX_NE 64      /* largest particle number per spin handled on device  */
+
+typedef struct lecqmc_ctx lecqmc_ctx;
+typedef struct lecqmc_walker lecqmc_walker;
+
+/* Lattice (host arrays, copied at walker creation; caller keeps ownership). */
+typedef struct {
+  int32_t n_sites, n_bonds, n_colors;
+  const int32_t *bond_i, *bond_j, *bond_color; /* [n_bonds]; colours 0..n_colors-1 */
+  const double *bond_h;                        /* [n_bonds] hopping element h_ij   */
+  const double *onsite;                        /* [n_sites] eps_i, or NULL          */
+  const int32_t *sublattice;                   /* [n_sites] 0..n_sublattices-1, or NULL */
+  int32_t n_sublattices, n_cells;              /* n_cells <= 0 means n_sites        */
+} lecqmc_lattice;
+
+typedef struct {
+  double U, beta, dtau;
+  int32_t n_stab;           /* slices per QR stabilisation, >= 1              */
+  int32_t n_up, n_dn;       /* 0..min(n_sites, LECQMC_MAX_NE)                 */
+  uint64_t seed, walker_id; /* key of the counter-based generator             */
+  int32_t precision;        /* LECQMC_FP64                                    */
+  int32_t flags;            /* LECQMC_NO_FOCK | LECQMC_NO_FLIPS               */
+  double wrap_tol;          /* max |A_wrap - A_fresh| diagonal (<= 0: 1e-8)   */
+} lecqmc_params;
+
+typedef struct {
+  int64_t flip_attempts, flip_accepts;   /* cumulative since creation          */
+  int64_t swap_attempts, swap_accepts;
+  double max_wrap_err;                   /* max over block starts               */
+  double logw_drift;                     /* max |tracked - fresh| log W at beta */
+  int64_t qr_shifted;                    /* QR calls that needed the shifted retry */
+  uint64_t sweeps;                       /* sweep counter                       */
+} lecqmc_sweep_stats;
+
+/* Context: device ordinal, a borrowed hipStream_t (NULL = the library makes
+ * its own), and the device-memory budget used for admission (0 = no limit). */
+int lecqmc_ctx_create(int device, void *hip_stream_or_null, size_t hbm_budget_bytes, lecqmc_ctx **out);
+/* Destroying a context that still owns walkers fails with LECQMC_ESTATE. */
+int lecqmc_ctx_destroy(lecqmc_ctx *ctx);
+int lecqmc_ctx_synchronize(lecqmc_ctx *ctx);
+size_t lecqmc_ctx_bytes_in_use(const lecqmc_ctx *ctx);
+/* Per-phase device timing: when enabled, every sweep records HIP events on
+ * the context's stream around its three launches (left stack, forward pass,
+ * Fock phase).  phase_times synchronises, returns the summed milliseconds and
+ * launch counts per phase since the last call, and resets them. */
+int lecqmc_ctx_set_timing(lecqmc_ctx *ctx, int32_t enable);
+int lecqmc_ctx_phase_times(lecqmc_ctx *ctx, double ms[3], int64_t counts[3]);
+
+/* Device bytes one walker needs (right and left stacks dominate:
+ * 2 * (2 n + 1) * N * Ne * 8 bytes); 0 if the input is invalid. */
+size_t lecqmc_footprint_bytes(const lecqmc_lattice *lat, const lecqmc_params *par);
+
+/* Create a walker: copies the lattice, builds the model tables, draws the
+ * fields (fields_or_null == NULL: s = +1 iff U(INIT_FIELD) < 1/2) and the
+ * occupation (NULL: partial Fisher-Yates shuffle) or takes the given ones,
+ * fields [L_tau][n_sites] int8 (+-1), occupations int32 distinct sites in
+ * column order.  Computes the fresh weight.  -2 if over the budget. */
+int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, const lecqmc_params *par,
+                         const int8_t *fields_or_null, const int32_t *occ_up_or_null,
+                         const int32_t *occ_dn_or_null, lecqmc_walker **out);
+int lecqmc_destroy_walker(lecqmc_walker *w);
+
+/* n_sweeps full sweeps; do_measure != 0 accumulates estimators at the
+ * interior stabilisation boundaries (tau = beta when there is one block). */
+int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measure);
+/* The same for n walkers of one context in one launch per phase; shapes
+ * may differ between walkers. */
+int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure);
+
+/* Fresh log|W| and sign from the current (eta, s) (right chain + QR). */
+int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);
+/* Weight carried by the chain (updated by every accepted move, reset to the
+ * fresh value at tau = beta of each sweep). */
+int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);
+
+/* Sign-weighted accumulators since the last reset; layout:
+ *  [0] sum sign  [1] number of measurements  [2] double occupancy per site
+ *  [3] kinetic energy per site  [4] S_par(q=0) = (1/L_c) sum_ij <SxSx+SySy>
+ *  [5] S_zz(q=0) total  [6] onsite energy per site  [7] density per site
+ *  [8 .. 8+ns^2) S_zz(q=0)_ab  [.. +ns^2) S_par(q=0)_ab
+ *  if n_sites <= 64: <S_i.S_j> (N^2), <n_i n_j> (N^2), <n_i up> (N), <n_i dn> (N)
+ * every entry already multiplied by the sign of the configuration. */
+int64_t lecqmc_obs_size(const lecqmc_walker *w);
+int lecqmc_measure(lecqmc_walker *w, double *out, int64_t n);
+int lecqmc_reset_measure(lecqmc_walker *w);
+int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st);
+
+/* State access (host buffers): fields [L_tau][N], occupations, sweep counter. */
+int lecqmc_get_state(lecqmc_walker *w, int8_t *fields, int32_t *occ_up, int32_t *occ_dn,
+                     uint64_t *sweep_counter);
+int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const int32_t *occ_up,
+                     const int32_t *occ_dn, uint64_t sweep_counter);
+
+/* Parity surface (fresh recomputation, small systems):
+ * G_ij = <c_i c_j^dag> at slice boundary b in 0..L_tau, N x N row-major. */
+int lecqmc_green(lecqmc_walker *w, int32_t boundary, int32_t spin, double *G);
+/* r = r_up r_dn for flipping s_{slice, site} (slice 0-based), not applied. */
+int lecqmc_flip_ratio(lecqmc_walker *w, int32_t slice, int32_t site, double *ratio);
+/* Remove occupied index k_index of spin, add empty site j: weight ratio of the
+ * composite move from a fresh right stack, not applied. */
+int lecqmc_swap_ratio(lecqmc_walker *w, int32_t spin, int32_t k_index, int32_t j_site, double *ratio);
+
+const char *lecqmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,606 @@
+// Host side of the C ABI declared in include/lecqmc.h: validation, model
+// tables, device-memory layout of a walker, and kernel orchestration.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/lecqmc.h"
+#include "lecqmc_internal.h"
+
+using namespace lecqmc;
+
+static thread_local char g_err[512];
+
+static int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(LECQMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct lecqmc_ctx {
+  int device;
+  hipStream_t stream;
+  bool own_stream;
+  size_t budget, used;
+  WalkerDesc *d_batch;
+  int batch_cap;
+  int live_walkers;
+  bool timing;
+  struct Rec { int phase; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+static hipEvent_t take_event(lecqmc_ctx *c) {
+  if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// launch one phase, bracketed by events when timing is on
+template <typename F>
+static hipError_t timed(lecqmc_ctx *c, int phase, F launch) {
+  if (!c->timing) return launch();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  hipError_t e = hipEventRecord(a, c->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+  c->recs.push_back({phase, a, b});
+  return e;
+}
+
+struct lecqmc_walker {
+  lecqmc_ctx *ctx;
+  WalkerDesc h;          // descriptor with device pointers
+  WalkerDesc *d_desc;    // device copy
+  void *dmem;
+  size_t bytes;
+  double *d_green;
+  int N, L, nblk, ne[2], mmax, nobs;
+};
+
+extern "C" const char *lecqmc_last_error(void) { return g_err; }
+
+// ---------------------------------------------------------------------------
+// validation and memory plan
+// ---------------------------------------------------------------------------
+static int validate(const lecqmc_lattice *lat, const lecqmc_params *par, int *L_out) {
+  if (!lat || !par) return fail(LECQMC_EINVAL, "null lattice or params");
+  const int N = lat->n_sites;
+  if (N <= 0 || lat->n_bonds < 0 || lat->n_colors < 0 || (lat->n_bonds > 0 && lat->n_colors <= 0))
+    return fail(LECQMC_EINVAL, "bad lattice sizes");
+  if (lat->n_bonds > 0 && (!lat->bond_i || !lat->bond_j || !lat->bond_color || !lat->bond_h))
+    return fail(LECQMC_EINVAL, "missing bond arrays");
+  if (par->n_up < 0 || par->n_up > N || par->n_dn < 0 || par->n_dn > N)
+    return fail(LECQMC_EINVAL, "particle number out of [0, n_sites]");
+  if (par->n_up > LECQMC_MAX_NE || par->n_dn > LECQMC_MAX_NE)
+    return fail(LECQMC_EINVAL, "particle number per spin above %d", LECQMC_MAX_NE);
+  if (par->n_stab <= 0) return fail(LECQMC_EINVAL, "n_stab must be >= 1");
+  if (!(par->dtau > 0.0) || !(par->beta > 0.0)) return fail(LECQMC_EINVAL, "beta and dtau must be > 0");
+  if (!(par->U >= 0.0)) return fail(LECQMC_EINVAL, "U must be >= 0 (spin-channel decoupling)");
+  if (par->precision != LECQMC_FP64) return fail(LECQMC_EINVAL, "unsupported precision %d", par->precision);
+  const double Lf = par->beta / par->dtau;
+  const long L = lround(Lf);
+  if (L <= 0 || fabs(Lf - (double)L) > 1e-9 * (Lf > 1 ? Lf : 1)) return fail(LECQMC_EINVAL, "beta/dtau not integral");
+  if ((double)L * N > 2.0e9) return fail(LECQMC_EINVAL, "field array too large");
+  std::vector<int> seen(N, -1);
+  for (int b = 0; b < lat->n_bonds; ++b) {
+    const int i = lat->bond_i[b], j = lat->bond_j[b], c = lat->bond_color[b];
+    if (i < 0 || i >= N || j < 0 || j >= N || i == j || c < 0 || c >= lat->n_colors)
+      return fail(LECQMC_EINVAL, "bad bond %d", b);
+  }
+  for (int c = 0; c < lat->n_colors; ++c)
+    for (int b = 0; b < lat->n_bonds; ++b) {
+      if (lat->bond_color[b] != c) continue;
+      const int i = lat->bond_i[b], j = lat->bond_j[b];
+      if (seen[i] == c || seen[j] == c) return fail(LECQMC_EINVAL, "colour %d has a shared site", c);
+      seen[i] = c;
+      seen[j] = c;
+    }
+  const int ns = (lat->sublattice && lat->n_sublattices > 0) ? lat->n_sublattices : 1;
+  if (ns > 8) return fail(LECQMC_EINVAL, "at most 8 sublattices");
+  if (lat->sublattice)
+    for (int i = 0; i < N; ++i)
+      if (lat->sublattice[i] < 0 || lat->sublattice[i] >= ns) return fail(LECQMC_EINVAL, "bad sublattice index");
+  *L_out = (int)L;
+  return 0;
+}
+
+struct Plan {
+  size_t off_sc, off_desc, off_s, off_occ[2], off_LS[2], off_RQ[2], off_RV[2], off_Minv[2], off_PhiR[2], off_X[2],
+      off_T[2], off_Aw[2], off_fq, off_fw, off_fVp, off_fgc, off_fgs, off_fv, off_frho, off_fmark, off_obs,
+      off_dbg, off_col, off_bi, off_bj, off_bdiag, off_boff, off_bh, off_epsf, off_eps, off_sub;
+  size_t total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int obs_count(int N, int ns) { return 8 + 2 * ns * ns + (N <= 64 ? 2 * N * N + 2 * N : 0); }
+
+static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int ncol, int ns) {
+  Plan p;
+  const int nb = (L + nstab - 1) / nstab;
+  const int mmax = std::max(1, std::max(ne0, ne1));
+  const int ne[2] = {ne0, ne1};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + (bytes ? bytes : 8)); return r; };
+  p.off_sc = take(sizeof(Scalars));
+  p.off_desc = take(sizeof(WalkerDesc));
+  p.off_s = take((size_t)L * N);
+  for (int s = 0; s < 2; ++s) p.off_occ[s] = take(sizeof(int) * (size_t)N);
+  for (int s = 0; s < 2; ++s) {
+    const size_t blk = (size_t)N * ne[s] * sizeof(double);
+    p.off_LS[s] = take(blk * (nb + 1));
+    p.off_RQ[s] = take(blk * nb);
+    p.off_RV[s] = take(sizeof(double) * (size_t)ne[s] * ne[s] * nb);
+    p.off_Minv[s] = take(sizeof(double) * (size_t)ne[s] * ne[s]);
+    p.off_PhiR[s] = take(blk);
+    p.off_X[s] = take(blk);
+    p.off_T[s] = take(blk);
+    p.off_Aw[s] = take(sizeof(double) * N);
+  }
+  p.off_fq = take(sizeof(double) * (size_t)nb * N);
+  p.off_fw = take(sizeof(double) * N);
+  p.off_fVp = take(sizeof(double) * (size_t)nb * mmax * mmax);
+  p.off_fgc = take(sizeof(double) * (size_t)nb * mmax);
+  p.off_fgs = take(sizeof(double) * (size_t)nb * mmax);
+  p.off_fv = take(sizeof(double) * (size_t)nb * mmax);
+  p.off_frho = take(sizeof(double) * nb);
+  p.off_fmark = take(sizeof(int) * (size_t)N);
+  p.off_obs = take(sizeof(double) * obs_count(N, ns));
+  p.off_dbg = take(sizeof(double) * (N <= 64 ? std::max(8, 2 * N * N) : 8));
+  p.off_col = take(sizeof(int) * (ncol + 1));
+  p.off_bi = take(sizeof(int) * nbonds);
+  p.off_bj = take(sizeof(int) * nbonds);
+  p.off_bdiag = take(sizeof(double) * nbonds);
+  p.off_boff = take(sizeof(double) * nbonds);
+  p.off_bh = take(sizeof(double) * nbonds);
+  p.off_epsf = take(sizeof(double) * N);
+  p.off_eps = take(sizeof(double) * N);
+  p.off_sub = take(sizeof(int) * N);
+  p.total = o;
+  return p;
+}
+
+extern "C" size_t lecqmc_footprint_bytes(const lecqmc_lattice *lat, const lecqmc_params *par) {
+  int L = 0;
+  if (validate(lat, par, &L)) return 0;
+  const int ns = (lat->sublattice && lat->n_sublattices > 0) ? lat->n_sublattices : 1;
+  return make_plan(lat->n_sites, L, par->n_stab, par->n_up, par->n_dn, lat->n_bonds, lat->n_colors, ns).total;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int lecqmc_ctx_create(int device, void *stream, size_t budget, lecqmc_ctx **out) {
+  if (!out) return fail(LECQMC_EINVAL, "null out");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(LECQMC_EINVAL, "device %d not present (%d devices)", device, ndev);
+  HIPCHK(hipSetDevice(device));
+  lecqmc_ctx *c = new lecqmc_ctx();
+  c->device = device;
+  c->budget = budget;
+  c->used = 0;
+  c->d_batch = nullptr;
+  c->batch_cap = 0;
+  c->timing = false;
+  c->live_walkers = 0;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+    c->own_stream = false;
+  } else {
+    hipError_t e = hipStreamCreate(&c->stream);
+    if (e != hipSuccess) { delete c; return fail(LECQMC_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
+    c->own_stream = true;
+  }
+  *out = c;
+  return 0;
+}
+
+extern "C" int lecqmc_ctx_destroy(lecqmc_ctx *c) {
+  if (!c) return 0;
+  if (c->live_walkers > 0) return fail(LECQMC_ESTATE, "context still owns %d walker(s)", c->live_walkers);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->d_batch) (void)hipFree(c->d_batch);
+  for (auto &r : c->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return 0;
+}
+
+extern "C" int lecqmc_ctx_synchronize(lecqmc_ctx *c) {
+  if (!c) return fail(LECQMC_EINVAL, "null context");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+extern "C" size_t lecqmc_ctx_bytes_in_use(const lecqmc_ctx *c) { return c ? c->used : 0; }
+
+extern "C" int lecqmc_ctx_set_timing(lecqmc_ctx *c, int32_t enable) {
+  if (!c) return fail(LECQMC_EINVAL, "null context");
+  c->timing = enable != 0;
+  return 0;
+}
+
+extern "C" int lecqmc_ctx_phase_times(lecqmc_ctx *c, double ms[3], int64_t counts[3]) {
+  if (!c || !ms || !counts) return fail(LECQMC_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int p = 0; p < 3; ++p) { ms[p] = 0.0; counts[p] = 0; }
+  for (auto &r : c->recs) {
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.phase] += t;
+    counts[r.phase] += 1;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// walker
+// ---------------------------------------------------------------------------
+static int check_status(lecqmc_walker *w) {
+  Scalars sc;
+  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  if (sc.status & 4) return fail(LECQMC_EUNSTABLE, "singular P^T B P or QR breakdown");
+  return 0;
+}
+
+extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, const lecqmc_params *par,
+                                    const int8_t *fields, const int32_t *occ_up, const int32_t *occ_dn,
+                                    lecqmc_walker **out) {
+  if (!ctx || !out) return fail(LECQMC_EINVAL, "null context or out");
+  int L = 0;
+  if (int rc = validate(lat, par, &L)) return rc;
+  const int N = lat->n_sites;
+  const int ns = (lat->sublattice && lat->n_sublattices > 0) ? lat->n_sublattices : 1;
+  const int ne[2] = {par->n_up, par->n_dn};
+  for (int s = 0; s < 2; ++s) {
+    const int32_t *g = s == 0 ? occ_up : occ_dn;
+    if (!g) continue;
+    std::vector<char> used(N, 0);
+    for (int a = 0; a < ne[s]; ++a) {
+      if (g[a] < 0 || g[a] >= N || used[g[a]]) return fail(LECQMC_EINVAL, "bad occupation list (spin %d)", s);
+      used[g[a]] = 1;
+    }
+  }
+  const Plan p = make_plan(N, L, par->n_stab, ne[0], ne[1], lat->n_bonds, lat->n_colors, ns);
+  if (ctx->budget && ctx->used + p.total > ctx->budget)
+    return fail(LECQMC_ENOMEM, "walker needs %zu bytes, %zu of %zu in use", p.total, ctx->used, ctx->budget);
+  HIPCHK(hipSetDevice(ctx->device));
+  void *dmem = nullptr;
+  HIPCHK(hipMalloc(&dmem, p.total));
+  char *base = (char *)dmem;
+
+  lecqmc_walker *w = new lecqmc_walker();
+  w->ctx = ctx;
+  w->dmem = dmem;
+  w->bytes = p.total;
+  w->d_green = nullptr;
+  w->N = N;
+  w->L = L;
+  w->nblk = (L + par->n_stab - 1) / par->n_stab;
+  w->ne[0] = ne[0];
+  w->ne[1] = ne[1];
+  w->mmax = std::max(1, std::max(ne[0], ne[1]));
+  w->nobs = obs_count(N, ns);
+
+  WalkerDesc &d = w->h;
+  memset(&d, 0, sizeof d);
+  d.N = N; d.L = L; d.nstab = par->n_stab; d.nblk = w->nblk; d.ncol = lat->n_colors; d.nbonds = lat->n_bonds;
+  d.nsub = ns; d.ncells = lat->n_cells > 0 ? lat->n_cells : N; d.flags = par->flags; d.nobs = w->nobs;
+  d.ne[0] = ne[0]; d.ne[1] = ne[1]; d.mmax = w->mmax;
+  d.seed = par->seed; d.wid = par->walker_id;
+  // Ising decoupling in the spin channel: cosh(lambda) = exp(dtau U / 2)
+  const double lambda = acosh(exp(par->dtau * par->U / 2.0));
+  d.elam = exp(lambda);
+  d.emlam = exp(-lambda);
+  d.delta_dn_s = exp(-2.0 * lambda) - 1.0;   // sigma * s = +1 flipped to -1
+  d.delta_up_s = exp(2.0 * lambda) - 1.0;    // sigma * s = -1 flipped to +1
+  d.wrap_tol = par->wrap_tol > 0 ? par->wrap_tol : 1e-8;
+  d.sc = (Scalars *)(base + p.off_sc);
+  d.s = (int8_t *)(base + p.off_s);
+  for (int s = 0; s < 2; ++s) {
+    d.occ[s] = (int *)(base + p.off_occ[s]);
+    d.LS[s] = (double *)(base + p.off_LS[s]);
+    d.RQ[s] = (double *)(base + p.off_RQ[s]);
+    d.RV[s] = (double *)(base + p.off_RV[s]);
+    d.Minv[s] = (double *)(base + p.off_Minv[s]);
+    d.PhiR[s] = (double *)(base + p.off_PhiR[s]);
+    d.X[s] = (double *)(base + p.off_X[s]);
+    d.T[s] = (double *)(base + p.off_T[s]);
+    d.Aw[s] = (double *)(base + p.off_Aw[s]);
+  }
+  d.fq = (double *)(base + p.off_fq);
+  d.fw = (double *)(base + p.off_fw);
+  d.fVp = (double *)(base + p.off_fVp);
+  d.fgc = (double *)(base + p.off_fgc);
+  d.fgs = (double *)(base + p.off_fgs);
+  d.fv = (double *)(base + p.off_fv);
+  d.frho = (double *)(base + p.off_frho);
+  d.fmark = (int *)(base + p.off_fmark);
+  d.obs = (double *)(base + p.off_obs);
+  d.dbg = (double *)(base + p.off_dbg);
+  int *col_start = (int *)(base + p.off_col);
+  int *bi = (int *)(base + p.off_bi);
+  int *bj = (int *)(base + p.off_bj);
+  double *bdiag = (double *)(base + p.off_bdiag);
+  double *boff = (double *)(base + p.off_boff);
+  double *bh = (double *)(base + p.off_bh);
+  double *epsf = (double *)(base + p.off_epsf);
+  double *eps = (double *)(base + p.off_eps);
+  int *sub = (int *)(base + p.off_sub);
+  d.col_start = col_start; d.bi = bi; d.bj = bj; d.bdiag = bdiag; d.boff = boff; d.bh = bh;
+  d.eps_fac = epsf; d.eps = eps; d.sub = sub;
+  w->d_desc = (WalkerDesc *)(base + p.off_desc);
+
+  // model tables: bonds grouped by colour (input order inside a colour),
+  // 2x2 bond exponential e^{-dtau h sigma_x} = cosh(dtau h) 1 - sinh(dtau h) sigma_x
+  std::vector<int> hcol(lat->n_colors + 1), hbi, hbj;
+  std::vector<double> hdiag, hoff, hh;
+  for (int c = 0; c < lat->n_colors; ++c) {
+    hcol[c] = (int)hbi.size();
+    for (int b = 0; b < lat->n_bonds; ++b) {
+      if (lat->bond_color[b] != c) continue;
+      const double h = lat->bond_h[b];
+      hbi.push_back(lat->bond_i[b]);
+      hbj.push_back(lat->bond_j[b]);
+      hdiag.push_back(cosh(par->dtau * h));
+      hoff.push_back(-sinh(par->dtau * h));
+      hh.push_back(h);
+    }
+  }
+  hcol[lat->n_colors] = (int)hbi.size();
+  std::vector<double> hepsf(N), heps(N);
+  std::vector<int> hsub(N);
+  for (int i = 0; i < N; ++i) {
+    heps[i] = lat->onsite ? lat->onsite[i] : 0.0;
+    hepsf[i] = exp(-par->dtau * heps[i]);
+    hsub[i] = lat->sublattice ? lat->sublattice[i] : 0;
+  }
+  auto cleanup = [&](int rc) { (void)hipFree(dmem); delete w; return rc; };
+  auto up = [&](void *dst, const void *src, size_t n) -> hipError_t {
+    return n ? hipMemcpy(dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  hipError_t e = hipMemset(dmem, 0, p.total);
+  if (e == hipSuccess) e = up(col_start, hcol.data(), sizeof(int) * hcol.size());
+  if (e == hipSuccess) e = up(bi, hbi.data(), sizeof(int) * hbi.size());
+  if (e == hipSuccess) e = up(bj, hbj.data(), sizeof(int) * hbj.size());
+  if (e == hipSuccess) e = up(bdiag, hdiag.data(), sizeof(double) * hdiag.size());
+  if (e == hipSuccess) e = up(boff, hoff.data(), sizeof(double) * hoff.size());
+  if (e == hipSuccess) e = up(bh, hh.data(), sizeof(double) * hh.size());
+  if (e == hipSuccess) e = up(epsf, hepsf.data(), sizeof(double) * N);
+  if (e == hipSuccess) e = up(eps, heps.data(), sizeof(double) * N);
+  if (e == hipSuccess) e = up(sub, hsub.data(), sizeof(int) * N);
+  if (e == hipSuccess && fields) {
+    std::vector<int8_t> f((size_t)L * N);
+    for (size_t t = 0; t < f.size(); ++t) f[t] = fields[t] > 0 ? 1 : -1;
+    e = up(d.s, f.data(), f.size());
+  }
+  if (e == hipSuccess && occ_up) e = up(d.occ[0], occ_up, sizeof(int) * ne[0]);
+  if (e == hipSuccess && occ_dn) e = up(d.occ[1], occ_dn, sizeof(int) * ne[1]);
+  if (e == hipSuccess) e = up(w->d_desc, &d, sizeof d);
+  if (e != hipSuccess) return cleanup(fail(LECQMC_EDEVICE, "upload: %s", hipGetErrorString(e)));
+  const int draw_occ = (occ_up ? 0 : 1) | (occ_dn ? 0 : 2);
+  if (!fields || draw_occ) e = launch_init(w->d_desc, fields ? 0 : 1, draw_occ, ctx->stream);
+  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, w->mmax, 1, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return cleanup(fail(LECQMC_EDEVICE, "init: %s", hipGetErrorString(e)));
+  ctx->used += p.total;
+  ctx->live_walkers += 1;
+  if (int rc = check_status(w)) { lecqmc_destroy_walker(w); return rc; }
+  *out = w;
+  return 0;
+}
+
+extern "C" int lecqmc_destroy_walker(lecqmc_walker *w) {
+  if (!w) return 0;
+  (void)hipSetDevice(w->ctx->device);
+  (void)hipStreamSynchronize(w->ctx->stream);
+  if (w->d_green) (void)hipFree(w->d_green);
+  (void)hipFree(w->dmem);
+  w->ctx->used -= w->bytes;
+  w->ctx->live_walkers -= 1;
+  delete w;
+  return 0;
+}
+
+extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measure) {
+  if (!w || n_sweeps < 0) return fail(LECQMC_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  hipStream_t st = w->ctx->stream;
+  lecqmc_ctx *c = w->ctx;
+  for (int t = 0; t < n_sweeps; ++t) {
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, w->mmax, st); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, w->mmax, do_measure, st); }));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, w->mmax, st); }));
+  }
+  return 0;
+}
+
+extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure) {
+  if (!ws || n <= 0 || n_sweeps < 0) return fail(LECQMC_EINVAL, "bad arguments");
+  lecqmc_ctx *c = ws[0]->ctx;
+  int mm = 1;
+  std::vector<WalkerDesc> hd(n);
+  for (int t = 0; t < n; ++t) {
+    if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers of a batch must share one context");
+    mm = std::max(mm, ws[t]->mmax);
+    hd[t] = ws[t]->h;
+  }
+  HIPCHK(hipSetDevice(c->device));
+  if (c->batch_cap < n) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->d_batch) HIPCHK(hipFree(c->d_batch));
+    HIPCHK(hipMalloc(&c->d_batch, sizeof(WalkerDesc) * n));
+    c->batch_cap = n;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
+  for (int t = 0; t < n_sweeps; ++t) {
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(c->d_batch, n, mm, c->stream); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(c->d_batch, n, mm, do_measure, c->stream); }));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(c->d_batch, n, mm, c->stream); }));
+  }
+  return 0;
+}
+
+extern "C" int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign) {
+  if (!w || !log_abs_w || !sign) return fail(LECQMC_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, w->mmax, 0, w->ctx->stream));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  Scalars sc;
+  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  *log_abs_w = sc.fresh_logw;
+  *sign = sc.fresh_sign;
+  return (sc.status & 4) ? fail(LECQMC_EUNSTABLE, "singular P^T B P") : 0;
+}
+
+extern "C" int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign) {
+  if (!w || !log_abs_w || !sign) return fail(LECQMC_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  Scalars sc;
+  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  *log_abs_w = sc.logw;
+  *sign = sc.sign;
+  return 0;
+}
+
+extern "C" int64_t lecqmc_obs_size(const lecqmc_walker *w) { return w ? w->nobs : 0; }
+
+extern "C" int lecqmc_measure(lecqmc_walker *w, double *out, int64_t n) {
+  if (!w || !out || n < w->nobs) return fail(LECQMC_EINVAL, "output too small (%d needed)", w ? w->nobs : 0);
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemcpy(out, w->h.obs, sizeof(double) * w->nobs, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+extern "C" int lecqmc_reset_measure(lecqmc_walker *w) {
+  if (!w) return fail(LECQMC_EINVAL, "null walker");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemset(w->h.obs, 0, sizeof(double) * w->nobs));
+  return 0;
+}
+
+extern "C" int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st) {
+  if (!w || !st) return fail(LECQMC_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  Scalars sc;
+  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  st->flip_attempts = sc.flip_att;
+  st->flip_accepts = sc.flip_acc;
+  st->swap_attempts = sc.swap_att;
+  st->swap_accepts = sc.swap_acc;
+  st->max_wrap_err = sc.max_wrap;
+  st->logw_drift = sc.logw_drift;
+  st->qr_shifted = sc.qr_shifted;
+  st->sweeps = sc.sweep;
+  return 0;
+}
+
+extern "C" int lecqmc_get_state(lecqmc_walker *w, int8_t *fields, int32_t *occ_up, int32_t *occ_dn,
+                                uint64_t *sweep_counter) {
+  if (!w) return fail(LECQMC_EINVAL, "null walker");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  if (fields) HIPCHK(hipMemcpy(fields, w->h.s, (size_t)w->L * w->N, hipMemcpyDeviceToHost));
+  if (occ_up && w->ne[0]) HIPCHK(hipMemcpy(occ_up, w->h.occ[0], sizeof(int) * w->ne[0], hipMemcpyDeviceToHost));
+  if (occ_dn && w->ne[1]) HIPCHK(hipMemcpy(occ_dn, w->h.occ[1], sizeof(int) * w->ne[1], hipMemcpyDeviceToHost));
+  if (sweep_counter) {
+    Scalars sc;
+    HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+    *sweep_counter = sc.sweep;
+  }
+  return 0;
+}
+
+extern "C" int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const int32_t *occ_up,
+                                const int32_t *occ_dn, uint64_t sweep_counter) {
+  if (!w) return fail(LECQMC_EINVAL, "null walker");
+  for (int s = 0; s < 2; ++s) {
+    const int32_t *g = s == 0 ? occ_up : occ_dn;
+    if (!g) continue;
+    std::vector<char> used(w->N, 0);
+    for (int a = 0; a < w->ne[s]; ++a) {
+      if (g[a] < 0 || g[a] >= w->N || used[g[a]]) return fail(LECQMC_EINVAL, "bad occupation list");
+      used[g[a]] = 1;
+    }
+  }
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  if (fields) {
+    std::vector<int8_t> f((size_t)w->L * w->N);
+    for (size_t t = 0; t < f.size(); ++t) f[t] = fields[t] > 0 ? 1 : -1;
+    HIPCHK(hipMemcpy(w->h.s, f.data(), f.size(), hipMemcpyHostToDevice));
+  }
+  if (occ_up && w->ne[0]) HIPCHK(hipMemcpy(w->h.occ[0], occ_up, sizeof(int) * w->ne[0], hipMemcpyHostToDevice));
+  if (occ_dn && w->ne[1]) HIPCHK(hipMemcpy(w->h.occ[1], occ_dn, sizeof(int) * w->ne[1], hipMemcpyHostToDevice));
+  Scalars sc;
+  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  sc.sweep = sweep_counter;
+  HIPCHK(hipMemcpy(w->h.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, w->mmax, 1, w->ctx->stream));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  return check_status(w);
+}
+
+extern "C" int lecqmc_green(lecqmc_walker *w, int32_t boundary, int32_t spin, double *G) {
+  if (!w || !G || boundary < 0 || boundary > w->L || spin < 0 || spin > 1) return fail(LECQMC_EINVAL, "bad arguments");
+  if (w->N > 8192) return fail(LECQMC_EINVAL, "green: N x N output limited to N <= 8192");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  if (!w->d_green) HIPCHK(hipMalloc(&w->d_green, sizeof(double) * (size_t)w->N * w->N));
+  HIPCHK(launch_green(w->d_desc, w->mmax, boundary, spin, w->d_green, w->ctx->stream));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemcpy(G, w->d_green, sizeof(double) * (size_t)w->N * w->N, hipMemcpyDeviceToHost));
+  return check_status(w);
+}
+
+extern "C" int lecqmc_flip_ratio(lecqmc_walker *w, int32_t slice, int32_t site, double *ratio) {
+  if (!w || !ratio || slice < 0 || slice >= w->L || site < 0 || site >= w->N) return fail(LECQMC_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(launch_flip_ratio(w->d_desc, w->mmax, slice, site, w->ctx->stream));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemcpy(ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
+  return check_status(w);
+}
+
+extern "C" int lecqmc_swap_ratio(lecqmc_walker *w, int32_t spin, int32_t k, int32_t j, double *ratio) {
+  if (!w || !ratio || spin < 0 || spin > 1) return fail(LECQMC_EINVAL, "bad arguments");
+  const int ne = w->ne[spin];
+  if (ne == 0 || ne == w->N || k < 0 || k >= ne || j < 0 || j >= w->N) return fail(LECQMC_EINVAL, "bad swap indices");
+  std::vector<int32_t> occ(ne);
+  HIPCHK(hipSetDevice(w->ctx->device));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemcpy(occ.data(), w->h.occ[spin], sizeof(int) * ne, hipMemcpyDeviceToHost));
+  for (int a = 0; a < ne; ++a)
+    if (occ[a] == j) return fail(LECQMC_EINVAL, "site %d is occupied", j);
+  HIPCHK(launch_swap_ratio(w->d_desc, w->mmax, spin, k, j, w->ctx->stream));
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemcpy(ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
+  return check_status(w);
+}

@@ -1,0 +1,1319 @@
+// gfx950 kernels of the canonical-ensemble DQMC hot path.
+//
+// One workgroup of 256 threads (4 wave64) owns one walker for the whole of a
+// phase; a batch launch gives every walker its own workgroup, so walkers of
+// different shapes share one launch.  Slater blocks (N x Ne, row-major FP64)
+// live in device memory and are streamed through L1/L2 by all 256 threads;
+// the Ne x Ne inverses (P^T B P)^{-1} stay in LDS during the forward pass,
+// where one wave runs the sequential Ising-flip chain (both spin species in
+// the two halves of the wave).
+//
+// Method (arXiv 2601.08552): weight of main text Eq. (1); HS-field updates
+// with the rank-1 fast update of the PQMC-like sweep (main text, "Ensemble
+// constrained QMC"); QR stabilisation every tau_w slices and the stabilized
+// QR update for particle removal / addition (SM Sec. I.A and I.B).
+#include <math.h>
+
+#include "lecqmc_internal.h"
+
+namespace lecqmc {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit multiplies by 0xD2511F53 / 0xCD9E8D57 with the Weyl key
+// schedule 0x9E3779B9 / 0xBB67AE85.  Counter (a, b, sweep, stream | id << 8),
+// key = seed; the double is the top 53 bits of (out0:out1) times 2^-53.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double uniform01(uint64_t seed, uint64_t wid, uint32_t stream,
+                                            uint32_t sweep, uint32_t a, uint32_t b) {
+  uint32_t x0 = a, x1 = b, x2 = sweep, x3 = (stream & 0xffu) | (uint32_t)((wid & 0xffffffull) << 8);
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+    const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  const uint64_t bits = ((uint64_t)x0 << 32) | x1;
+  return (double)(bits >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ int pick(double u, int n) {
+  int v = (int)floor(u * (double)n);
+  return v >= n ? n - 1 : v;
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout (dynamic): sized by the largest Ne of the launch (mm).
+// ---------------------------------------------------------------------------
+struct Lds {
+  double *red;    // 256   block reductions
+  double *Ms0;    // mm^2  inverse, spin up   (Fock phase: Hessenberg work)
+  double *Ms1;    // mm^2  inverse, spin down (Fock phase: permuted inverse)
+  double *A;      // mm^2  Gram / Cholesky / pivot work (Fock phase: reduced inverse)
+  double *B;      // mm^2  triangular inverse / output
+  double *uw;     // 2*64  flip-chain column vectors
+  double *vec;    // 8*64  small vectors
+  double *scal;   // 64    broadcast scalars
+  int *iscal;     // 320   broadcast integers + per-thread counts
+};
+
+size_t lds_bytes(int mm) {
+  if (mm < 1) mm = 1;
+  return sizeof(double) * (256 + 4 * (size_t)mm * mm + 2 * 64 + 8 * 64 + 64) + sizeof(int) * 320;
+}
+
+extern __shared__ double lds_raw[];
+
+__device__ Lds carve(int mm) {
+  if (mm < 1) mm = 1;
+  Lds L;
+  double *p = lds_raw;
+  L.red = p; p += 256;
+  L.Ms0 = p; p += mm * mm;
+  L.Ms1 = p; p += mm * mm;
+  L.A = p; p += mm * mm;
+  L.B = p; p += mm * mm;
+  L.uw = p; p += 2 * 64;
+  L.vec = p; p += 8 * 64;
+  L.scal = p; p += 64;
+  L.iscal = reinterpret_cast<int *>(p);
+  return L;
+}
+
+#define TID (static_cast<int>(threadIdx.x))
+#define SYNC() __syncthreads()
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ double wg_sum(double v, double *red) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  SYNC();
+  if ((TID & 63) == 0) red[TID >> 6] = v;
+  SYNC();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ double wg_max(double v, double *red) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  SYNC();
+  if ((TID & 63) == 0) red[TID >> 6] = v;
+  SYNC();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// ---------------------------------------------------------------------------
+// Propagation of N x m blocks (rows = sites): checkerboard colour passes and
+// the diagonal Ising/onsite factor.
+// ---------------------------------------------------------------------------
+__device__ void colour_pass(const WalkerDesc &w, double *X, int m, int c, bool inverse) {
+  const int b0 = w.col_start[c], nb = w.col_start[c + 1] - b0;
+  const int tot = nb * m;
+  for (int t = TID; t < tot; t += kThreads) {
+    const int b = b0 + t / m, a = t - (t / m) * m;
+    const int i = w.bi[b], j = w.bj[b];
+    const double d = w.bdiag[b], o = inverse ? -w.boff[b] : w.boff[b];
+    const double xi = X[(size_t)i * m + a], xj = X[(size_t)j * m + a];
+    X[(size_t)i * m + a] = d * xi + o * xj;
+    X[(size_t)j * m + a] = o * xi + d * xj;
+  }
+  SYNC();
+}
+// X <- E_K X : colour C-1 acts first
+__device__ void apply_ek(const WalkerDesc &w, double *X, int m) {
+  for (int c = w.ncol - 1; c >= 0; --c) colour_pass(w, X, m, c, false);
+}
+// X <- E_K^T X : colour 0 acts first
+__device__ void apply_ekT(const WalkerDesc &w, double *X, int m) {
+  for (int c = 0; c < w.ncol; ++c) colour_pass(w, X, m, c, false);
+}
+// X <- E_K^{-T} X : inverse colours, colour C-1 acts first
+__device__ void apply_ekinvT(const WalkerDesc &w, double *X, int m) {
+  for (int c = w.ncol - 1; c >= 0; --c) colour_pass(w, X, m, c, true);
+}
+// X <- D_l^{+-1} X for spin sp (l = 1..L)
+__device__ void apply_diag(const WalkerDesc &w, double *X, int m, int l, int sp, bool inverse) {
+  const int8_t *s = w.s + (size_t)(l - 1) * w.N;
+  const int tot = w.N * m;
+  for (int t = TID; t < tot; t += kThreads) {
+    const int i = t / m;
+    const int ss = sp == 0 ? s[i] : -s[i];
+    const double f = (ss > 0 ? w.elam : w.emlam) * w.eps_fac[i];
+    X[t] *= inverse ? 1.0 / f : f;
+  }
+  SYNC();
+}
+
+__device__ void fill_P(const WalkerDesc &w, int sp, double *X) {
+  const int m = w.ne[sp], tot = w.N * m;
+  for (int t = TID; t < tot; t += kThreads) X[t] = 0.0;
+  SYNC();
+  for (int a = TID; a < m; a += kThreads) X[(size_t)w.occ[sp][a] * m + a] = 1.0;
+  SYNC();
+}
+
+__device__ void copy_global(double *dst, const double *src, size_t n) {
+  for (size_t t = TID; t < n; t += kThreads) dst[t] = src[t];
+  SYNC();
+}
+
+// out[p][q] = sum_i X[i][p] Y[i][q] over rows i (optionally only sub[i] == a)
+__device__ void gram(const double *X, int mx, const double *Y, int my, int N, double *out,
+                     double *red, const int *sub = nullptr, int sa = 0) {
+  const int P = mx * my;
+  if (P == 0) { SYNC(); return; }
+  if (P <= kThreads) {
+    const int G = kThreads / P;
+    const int g = TID / P, p = TID - g * P;
+    double acc = 0.0;
+    if (g < G) {
+      const int pa = p / my, qb = p - pa * my;
+      for (int i = g; i < N; i += G)
+        if (!sub || sub[i] == sa) acc += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+    }
+    SYNC();
+    red[TID] = acc;
+    SYNC();
+    if (TID < P) {
+      double s = 0.0;
+      for (int gg = 0; gg < G; ++gg) s += red[gg * P + TID];
+      out[TID] = s;
+    }
+    SYNC();
+  } else {
+    for (int p = TID; p < P; p += kThreads) {
+      const int pa = p / my, qb = p - pa * my;
+      double acc = 0.0;
+      for (int i = 0; i < N; ++i)
+        if (!sub || sub[i] == sa) acc += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+      out[p] = acc;
+    }
+    SYNC();
+  }
+}
+
+// Cholesky G = R^T R in place (upper triangle of A); false on a non-positive pivot.
+__device__ bool cholesky(double *A, int m, double *scal) {
+  for (int j = 0; j < m; ++j) {
+    if (TID == 0) {
+      const double d = A[j * m + j];
+      scal[0] = d;
+      A[j * m + j] = d > 0.0 ? sqrt(d) : d;
+    }
+    SYNC();
+    if (!(scal[0] > 0.0)) { SYNC(); return false; }
+    const double r = A[j * m + j];
+    for (int c = j + 1 + TID; c < m; c += kThreads) A[j * m + c] /= r;
+    SYNC();
+    const int rem = m - j - 1;
+    for (int t = TID; t < rem * rem; t += kThreads) {
+      const int a = j + 1 + t / rem, c = j + 1 + t % rem;
+      if (c >= a) A[a * m + c] -= A[j * m + a] * A[j * m + c];
+    }
+    SYNC();
+  }
+  return true;
+}
+
+// Ri = R^{-1} (upper triangular), column by column
+__device__ void tri_inverse(const double *R, int m, double *Ri) {
+  for (int c = TID; c < m; c += kThreads) {
+    for (int a = c + 1; a < m; ++a) Ri[a * m + c] = 0.0;
+    Ri[c * m + c] = 1.0 / R[c * m + c];
+    for (int a = c - 1; a >= 0; --a) {
+      double s = 0.0;
+      for (int b = a + 1; b <= c; ++b) s += R[a * m + b] * Ri[b * m + c];
+      Ri[a * m + c] = -s / R[a * m + a];
+    }
+  }
+  SYNC();
+}
+
+// out = in * Ri (Ri upper triangular), written to out and out2 (if set)
+__device__ void right_tri_mul(const double *in, double *out, double *out2, int N, int m, const double *Ri) {
+  const int tot = N * m;
+  for (int t = TID; t < tot; t += kThreads) {
+    const int i = t / m, c = t - (t / m) * m;
+    const double *row = in + (size_t)i * m;
+    double s = 0.0;
+    for (int a = 0; a <= c; ++a) s += row[a] * Ri[a * m + c];
+    out[t] = s;
+    if (out2) out2[t] = s;
+  }
+  SYNC();
+}
+
+// Thin QR with positive diagonal by Cholesky QR, repeated (CholeskyQR2;
+// a shifted first pass and a third pass when the Gram matrix is not
+// numerically positive definite).  Phi (N x m) -> Q in q1 (and q2); the
+// triangular factor R = R_last ... R_1 goes to Vout (m x m, may be null).
+// tmp: N x m scratch distinct from Phi, q1, q2.  Vacc: m x m global scratch.
+// Returns sum_j log R_jj.
+__device__ double cholqr(const double *Phi, double *tmp, double *q1, double *q2, double *Vout,
+                         double *Vacc, int N, int m, Lds &L, Scalars *sc) {
+  if (m == 0) { SYNC(); return 0.0; }
+  bool shifted = false;
+  // pass 1: Phi -> tmp
+  gram(Phi, m, Phi, m, N, L.A, L.red);
+  if (!cholesky(L.A, m, L.scal)) {
+    gram(Phi, m, Phi, m, N, L.A, L.red);
+    if (TID == 0) {
+      double tr = 0.0;
+      for (int a = 0; a < m; ++a) tr += L.A[a * m + a];
+      const double shift = 11.0 * ((double)N * m + (double)m * (m + 1)) * 0x1.0p-53 * tr;
+      for (int a = 0; a < m; ++a) L.A[a * m + a] += shift;
+      sc->qr_shifted += 1;
+      sc->status |= 2;
+    }
+    SYNC();
+    cholesky(L.A, m, L.scal);
+    shifted = true;
+  }
+  for (int t = TID; t < m * m; t += kThreads) {
+    const int a = t / m, c = t % m;
+    Vacc[t] = c >= a ? L.A[t] : 0.0;
+  }
+  tri_inverse(L.A, m, L.B);
+  right_tri_mul(Phi, tmp, nullptr, N, m, L.B);
+  const int passes = shifted ? 3 : 2;
+  for (int pass = 1; pass < passes; ++pass) {
+    const double *in = (pass == 1) ? tmp : q1;
+    double *out = (pass == 1) ? q1 : tmp;
+    gram(in, m, in, m, N, L.A, L.red);
+    if (!cholesky(L.A, m, L.scal)) {
+      if (TID == 0) sc->status |= 4;
+    }
+    tri_inverse(L.A, m, L.B);
+    right_tri_mul(in, out, nullptr, N, m, L.B);
+    // Vacc <- R_pass * Vacc (both upper triangular) via B
+    for (int t = TID; t < m * m; t += kThreads) {
+      const int a = t / m, c = t % m;
+      double s = 0.0;
+      for (int b = a; b <= c; ++b) s += L.A[a * m + b] * Vacc[b * m + c];
+      L.B[t] = c >= a ? s : 0.0;
+    }
+    SYNC();
+    for (int t = TID; t < m * m; t += kThreads) Vacc[t] = L.B[t];
+    SYNC();
+  }
+  // final Q lives in q1 (2 passes) or tmp (3 passes)
+  const double *qf = (passes == 2) ? q1 : tmp;
+  const int tot = N * m;
+  for (int t = TID; t < tot; t += kThreads) {
+    const double v = qf[t];
+    if (passes != 2) q1[t] = v;
+    if (q2) q2[t] = v;
+  }
+  if (Vout)
+    for (int t = TID; t < m * m; t += kThreads) Vout[t] = Vacc[t];
+  SYNC();
+  double ld = 0.0;
+  for (int a = 0; a < m; ++a) ld += log(Vacc[a * m + a]);
+  SYNC();
+  return ld;
+}
+
+// Inverse by Gauss-Jordan elimination with partial pivoting.
+// M (LDS, m x m) is destroyed; Minv may be LDS or global.  log|det|, sign
+// and a singular flag are returned through scal / iscal.
+__device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logabs, int *sign) {
+  for (int t = TID; t < m * m; t += kThreads) Minv[t] = (t / m == t % m) ? 1.0 : 0.0;
+  if (TID == 0) { L.scal[2] = 0.0; L.iscal[1] = 1; L.iscal[2] = 0; }
+  SYNC();
+  double *fac = L.vec + 7 * 64;
+  for (int c = 0; c < m; ++c) {
+    if (TID == 0) {
+      int p = c;
+      double best = fabs(M[c * m + c]);
+      for (int r = c + 1; r < m; ++r)
+        if (fabs(M[r * m + c]) > best) { best = fabs(M[r * m + c]); p = r; }
+      L.iscal[0] = p;
+      L.scal[1] = M[p * m + c];
+      if (best == 0.0) L.iscal[2] = 1;
+      if (p != c) L.iscal[1] = -L.iscal[1];
+    }
+    SYNC();
+    if (L.iscal[2]) { SYNC(); *logabs = -INFINITY; *sign = 0; return false; }
+    const int p = L.iscal[0];
+    const double piv = L.scal[1];
+    if (p != c) {
+      for (int x = TID; x < m; x += kThreads) {
+        double t0 = M[c * m + x]; M[c * m + x] = M[p * m + x]; M[p * m + x] = t0;
+        double t1 = Minv[c * m + x]; Minv[c * m + x] = Minv[p * m + x]; Minv[p * m + x] = t1;
+      }
+      SYNC();
+    }
+    for (int x = TID; x < m; x += kThreads) { M[c * m + x] /= piv; Minv[c * m + x] /= piv; }
+    if (TID == 0) {
+      L.scal[2] += log(fabs(piv));
+      if (piv < 0.0) L.iscal[1] = -L.iscal[1];
+    }
+    SYNC();
+    for (int r = TID; r < m; r += kThreads) fac[r] = M[r * m + c];
+    SYNC();
+    for (int t = TID; t < m * m; t += kThreads) {
+      const int r = t / m, x = t % m;
+      if (r == c) continue;
+      M[r * m + x] -= fac[r] * M[c * m + x];
+      Minv[r * m + x] -= fac[r] * Minv[c * m + x];
+    }
+    SYNC();
+  }
+  *logabs = L.scal[2];
+  *sign = L.iscal[1];
+  SYNC();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Sequential Ising-flip chain over all sites of slice l (wave 0).
+// Lanes 0..31 carry spin up, lanes 32..63 spin down; lane h owns rows and
+// columns h and h + 32 of the spin's inverse (LDS).  Per site:
+//   a_s = Phi_R[i,:] M_s^{-1} Phi_L[:,i],  r_s = 1 + Delta_s a_s,  r = r_up r_dn,
+// accept if U(FLIP, sweep, l, i) < |r|; on acceptance the Sherman-Morrison
+// update M^{-1} -= (Delta/r)(M^{-1} Phi_L[:,i])(Phi_R[i,:] M^{-1}) and the row
+// scaling Phi_R[i,:] *= 1 + Delta.
+// ---------------------------------------------------------------------------
+__device__ void flip_slice(const WalkerDesc &w, int l, uint32_t sweep, Lds &L) {
+  if (TID < 64) {
+    const int lane = TID, sp = lane >> 5, h = lane & 31;
+    const int m = w.ne[sp];
+    double *Ms = sp ? L.Ms1 : L.Ms0;
+    double *PR = w.PhiR[sp];
+    const double *XX = w.X[sp];
+    double *wsh = L.uw + sp * 64;
+    int8_t *srow = w.s + (size_t)(l - 1) * w.N;
+    double logw = 0.0;
+    int sgn = 1;
+    long long nacc = 0;
+    double xr = 0.0;
+    for (int i = 0; i < w.N; ++i) {
+      if ((i & 63) == 0) {
+        const int ii = i + lane;
+        xr = ii < w.N ? uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)ii) : 0.0;
+      }
+      const double x = __shfl(xr, i & 63);
+      const int sv = srow[i];
+      const int ss = sp == 0 ? sv : -sv;
+      const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
+      const double *xrow = XX + (size_t)i * m;
+      double *prow = PR + (size_t)i * m;
+      double u0 = 0.0, u1 = 0.0, part = 0.0;
+      if (h < m) {
+        double acc = 0.0;
+        for (int q = 0; q < m; ++q) acc += Ms[h * m + q] * xrow[q];
+        u0 = acc;
+        part += prow[h] * acc;
+      }
+      if (h + 32 < m) {
+        double acc = 0.0;
+        for (int q = 0; q < m; ++q) acc += Ms[(h + 32) * m + q] * xrow[q];
+        u1 = acc;
+        part += prow[h + 32] * acc;
+      }
+      for (int o = 16; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+      const double rsp = 1.0 + delta * part;
+      const double roth = __shfl_xor(rsp, 32);
+      const double ratio = sp == 0 ? rsp * roth : roth * rsp;
+      if (x < fabs(ratio)) {
+        if (h < m) {
+          double acc = 0.0;
+          for (int p = 0; p < m; ++p) acc += prow[p] * Ms[p * m + h];
+          wsh[h] = acc;
+        }
+        if (h + 32 < m) {
+          double acc = 0.0;
+          for (int p = 0; p < m; ++p) acc += prow[p] * Ms[p * m + h + 32];
+          wsh[h + 32] = acc;
+        }
+        wave_fence();
+        const double c = delta / rsp;
+        if (h < m) {
+          const double cu = c * u0;
+          for (int b = 0; b < m; ++b) Ms[h * m + b] -= cu * wsh[b];
+        }
+        if (h + 32 < m) {
+          const double cu = c * u1;
+          for (int b = 0; b < m; ++b) Ms[(h + 32) * m + b] -= cu * wsh[b];
+        }
+        wave_fence();
+        if (h < m) prow[h] *= 1.0 + delta;
+        if (h + 32 < m) prow[h + 32] *= 1.0 + delta;
+        if (lane == 0) srow[i] = (int8_t)(-sv);
+        logw += log(fabs(ratio));
+        if (ratio < 0.0) sgn = -sgn;
+        ++nacc;
+        wave_fence();
+      }
+    }
+    if (lane == 0) {
+      L.scal[10] += logw;
+      L.scal[11] *= (double)sgn;
+      w.sc->flip_att += w.N;
+      w.sc->flip_acc += nacc;
+    }
+  }
+  SYNC();
+}
+
+// ---------------------------------------------------------------------------
+// Equal-time estimators (Wick) from A_s = Phi_R M_s^{-1} Phi_L at a fresh
+// boundary, accumulated sign-weighted in the observable layout of the ABI.
+// q = 0 sums use traces of Ne x Ne sublattice blocks, O(N Ne^2).
+// ---------------------------------------------------------------------------
+__device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *const XL[2],
+                              const double *Ms[2], int sgn, Lds &L) {
+  const int N = w.N, ns = w.nsub;
+  const double sg = (double)sgn;
+  // T_s = Phi_R M_s^{-1}
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    const int tot = N * m;
+    for (int t = TID; t < tot; t += kThreads) {
+      const int i = t / m, b = t - (t / m) * m;
+      double s = 0.0;
+      for (int a = 0; a < m; ++a) s += PR[sp][(size_t)i * m + a] * Ms[sp][a * m + b];
+      w.T[sp][t] = s;
+    }
+  }
+  SYNC();
+  // diagonal sums
+  double docc = 0.0, eon = 0.0, dens = 0.0;
+  double nsa[2][8];
+  for (int a = 0; a < 8; ++a) { nsa[0][a] = 0.0; nsa[1][a] = 0.0; }
+  for (int i = TID; i < N; i += kThreads) {
+    double ad[2];
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      double s = 0.0;
+      for (int b = 0; b < m; ++b) s += w.T[sp][(size_t)i * m + b] * XL[sp][(size_t)i * m + b];
+      ad[sp] = s;
+    }
+    docc += ad[0] * ad[1];
+    eon += w.eps[i] * (ad[0] + ad[1]);
+    dens += ad[0] + ad[1];
+    const int a = w.sub[i];
+    for (int q = 0; q < ns && q < 8; ++q)
+      if (q == a) { nsa[0][q] += ad[0]; nsa[1][q] += ad[1]; }
+  }
+  docc = wg_sum(docc, L.red);
+  eon = wg_sum(eon, L.red);
+  dens = wg_sum(dens, L.red);
+  double nup[8], ndn[8];
+  for (int a = 0; a < ns && a < 8; ++a) {
+    nup[a] = wg_sum(nsa[0][a], L.red);
+    ndn[a] = wg_sum(nsa[1][a], L.red);
+  }
+  // kinetic term: sum_b h_b (A_ij + A_ji) for both spins
+  double ek = 0.0;
+  for (int b = TID; b < w.nbonds; b += kThreads) {
+    const int i = w.bi[b], j = w.bj[b];
+    double s = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      for (int q = 0; q < m; ++q)
+        s += w.T[sp][(size_t)i * m + q] * XL[sp][(size_t)j * m + q] +
+             w.T[sp][(size_t)j * m + q] * XL[sp][(size_t)i * m + q];
+    }
+    ek += w.bh[b] * s;
+  }
+  ek = wg_sum(ek, L.red);
+  // sublattice traces
+  double *szz = w.obs + 8, *spar = w.obs + 8 + ns * ns;
+  double szz_tot = 0.0, spar_tot = 0.0;
+  const int mu = w.ne[0], md = w.ne[1];
+  for (int a = 0; a < ns; ++a)
+    for (int b = 0; b < ns; ++b) {
+      double same[2];
+      for (int sp = 0; sp < 2; ++sp) {
+        const int m = w.ne[sp];
+        // Y_a = sum_{i in a} X_i^T T_i  (m x m), trace(Y_a Y_b)
+        gram(XL[sp], m, w.T[sp], m, N, L.A, L.red, w.sub, a);
+        gram(XL[sp], m, w.T[sp], m, N, L.B, L.red, w.sub, b);
+        double tr = 0.0;
+        for (int t = TID; t < m * m; t += kThreads) {
+          const int p = t / m, q = t % m;
+          tr += L.A[p * m + q] * L.B[q * m + p];
+        }
+        tr = wg_sum(tr, L.red);
+        const double na = sp == 0 ? nup[a] : ndn[a], nb = sp == 0 ? nup[b] : ndn[b];
+        same[sp] = na * nb + (a == b ? na : 0.0) - tr;
+      }
+      const double cross = nup[a] * ndn[b] + ndn[a] * nup[b];
+      const double zz = 0.25 * (same[0] + same[1] - cross);
+      // Z^a = sum_{i in a} X_up,i^T T_dn,i ; Z'^b = sum_{j in b} T_up,j^T X_dn,j
+      gram(XL[0], mu, w.T[1], md, N, L.A, L.red, w.sub, a);
+      gram(w.T[0], mu, XL[1], md, N, L.B, L.red, w.sub, b);
+      double d1 = 0.0;
+      for (int t = TID; t < mu * md; t += kThreads) d1 += L.A[t] * L.B[t];
+      d1 = wg_sum(d1, L.red);
+      // Z'^a and Z^b
+      gram(w.T[0], mu, XL[1], md, N, L.A, L.red, w.sub, a);
+      gram(XL[0], mu, w.T[1], md, N, L.B, L.red, w.sub, b);
+      double d2 = 0.0;
+      for (int t = TID; t < mu * md; t += kThreads) d2 += L.A[t] * L.B[t];
+      d2 = wg_sum(d2, L.red);
+      const double pm = (a == b ? nup[a] : 0.0) - d1;
+      const double mp = (a == b ? ndn[a] : 0.0) - d2;
+      const double xy = 0.5 * (pm + mp);
+      if (TID == 0) {
+        szz[a * ns + b] += sg * zz / w.ncells;
+        spar[a * ns + b] += sg * xy / w.ncells;
+      }
+      szz_tot += zz;
+      spar_tot += xy;
+    }
+  if (TID == 0) {
+    w.obs[0] += sg;
+    w.obs[1] += 1.0;
+    w.obs[2] += sg * docc / N;
+    w.obs[3] += sg * ek / N;
+    w.obs[4] += sg * spar_tot / w.ncells;
+    w.obs[5] += sg * szz_tot / w.ncells;
+    w.obs[6] += sg * eon / N;
+    w.obs[7] += sg * dens / N;
+  }
+  SYNC();
+  if (N <= 64) {
+    // all-pair correlations from explicit A matrices (small lattices)
+    double *Au = w.dbg, *Ad = w.dbg + N * N;
+    for (int t = TID; t < N * N; t += kThreads) {
+      const int i = t / N, j = t % N;
+      double su = 0.0, sd = 0.0;
+      for (int q = 0; q < mu; ++q) su += w.T[0][(size_t)i * mu + q] * XL[0][(size_t)j * mu + q];
+      for (int q = 0; q < md; ++q) sd += w.T[1][(size_t)i * md + q] * XL[1][(size_t)j * md + q];
+      Au[t] = su;
+      Ad[t] = sd;
+    }
+    SYNC();
+    double *ss = w.obs + 8 + 2 * ns * ns, *nn = ss + N * N, *nu = nn + N * N, *nd = nu + N;
+    for (int t = TID; t < N * N; t += kThreads) {
+      const int i = t / N, j = t % N;
+      const double d = (i == j) ? 1.0 : 0.0;
+      const double uu = Au[i * N + i] * Au[j * N + j] + Au[j * N + i] * (d - Au[i * N + j]);
+      const double dd = Ad[i * N + i] * Ad[j * N + j] + Ad[j * N + i] * (d - Ad[i * N + j]);
+      const double ud = Au[i * N + i] * Ad[j * N + j];
+      const double du = Ad[i * N + i] * Au[j * N + j];
+      const double zz = 0.25 * (uu + dd - ud - du);
+      const double pm = Au[j * N + i] * (d - Ad[i * N + j]);
+      const double mp = Ad[j * N + i] * (d - Au[i * N + j]);
+      ss[t] += sg * (zz + 0.5 * (pm + mp));
+      nn[t] += sg * (uu + dd + ud + du);
+    }
+    for (int i = TID; i < N; i += kThreads) {
+      nu[i] += sg * Au[i * N + i];
+      nd[i] += sg * Ad[i * N + i];
+    }
+    SYNC();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Right chain from P with a QR at every block end; (Q_k, V_k) stored.
+// Returns sum_k sum_j log V_k,jj for spin sp.
+// ---------------------------------------------------------------------------
+__device__ double right_stack(const WalkerDesc &w, int sp, Lds &L) {
+  const int m = w.ne[sp], N = w.N;
+  double *Phi = w.PhiR[sp];
+  fill_P(w, sp, Phi);
+  double ld = 0.0;
+  for (int k = 1; k <= w.nblk; ++k) {
+    const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
+    for (int l = l0; l <= l1; ++l) {
+      apply_diag(w, Phi, m, l, sp, false);
+      apply_ek(w, Phi, m);
+    }
+    double *Q = w.RQ[sp] + (size_t)(k - 1) * N * m;
+    double *V = w.RV[sp] + (size_t)(k - 1) * m * m;
+    ld += cholqr(Phi, w.T[sp], Q, Phi, V, w.fVp, N, m, L, w.sc);
+  }
+  return ld;
+}
+
+// M = P^T Q_n and its inverse into Minv (global); returns log|det M|, sign.
+__device__ void inverse_at_beta(const WalkerDesc &w, int sp, Lds &L, double *logabs, int *sign) {
+  const int m = w.ne[sp], N = w.N;
+  const double *Qn = w.RQ[sp] + (size_t)(w.nblk - 1) * N * m;
+  for (int t = TID; t < m * m; t += kThreads) {
+    const int a = t / m, b = t % m;
+    L.A[t] = Qn[(size_t)w.occ[sp][a] * m + b];
+  }
+  SYNC();
+  if (m == 0) { *logabs = 0.0; *sign = 1; SYNC(); return; }
+  if (!gj_inverse(L.A, w.Minv[sp], m, L, logabs, sign)) {
+    if (TID == 0) w.sc->status |= 4;
+  }
+  SYNC();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *descs, int draw_fields, int draw_occ) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  if (draw_fields) {
+    const int tot = w.L * w.N;
+    for (int t = TID; t < tot; t += kThreads) {
+      const int l = t / w.N, i = t % w.N;
+      w.s[t] = uniform01(w.seed, w.wid, kInitField, 0, (uint32_t)l, (uint32_t)i) < 0.5 ? 1 : -1;
+    }
+  }
+  for (int sp = 0; sp < 2; ++sp) {
+    if ((draw_occ >> sp) & 1) {
+      for (int i = TID; i < w.N; i += kThreads) w.fmark[i] = i;
+      SYNC();
+      if (TID == 0) {
+        for (int a = 0; a < w.ne[sp]; ++a) {
+          const int j = a + pick(uniform01(w.seed, w.wid, kInitOcc, 0, (uint32_t)sp, (uint32_t)a), w.N - a);
+          const int t = w.fmark[a];
+          w.fmark[a] = w.fmark[j];
+          w.fmark[j] = t;
+          w.occ[sp][a] = w.fmark[a];
+        }
+      }
+      SYNC();
+    }
+  }
+}
+
+// Fresh log-weight from the current (eta, s): right stack + inverse at beta.
+__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *descs, int mm, int set_tracked) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  Lds L = carve(mm);
+  double la = 0.0;
+  int sg = 1;
+  for (int sp = 0; sp < 2; ++sp) {
+    la += right_stack(w, sp, L);
+    double l2;
+    int s2;
+    inverse_at_beta(w, sp, L, &l2, &s2);
+    la += l2;
+    sg *= s2;
+  }
+  if (TID == 0) {
+    w.sc->fresh_logw = la;
+    w.sc->fresh_sign = sg;
+    if (set_tracked) { w.sc->logw = la; w.sc->sign = sg; }
+  }
+}
+
+// Left stack: Y <- P; for k = n..1: Y <- D_l E_K^T Y over the block's slices
+// (last to first), thin QR, LS[k-1] = Q.  LS[n] = P.
+__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs, int mm) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  Lds L = carve(mm);
+  const int N = w.N;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    double *Y = w.X[sp];
+    fill_P(w, sp, Y);
+    copy_global(w.LS[sp] + (size_t)w.nblk * N * m, Y, (size_t)N * m);
+    for (int k = w.nblk; k >= 1; --k) {
+      const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
+      for (int l = l1; l >= l0; --l) {
+        apply_ekT(w, Y, m);
+        apply_diag(w, Y, m, l, sp, false);
+      }
+      double *Q = w.LS[sp] + (size_t)(k - 1) * N * m;
+      cholqr(Y, w.T[sp], Q, Y, nullptr, w.fVp, N, m, L, w.sc);
+    }
+  }
+}
+
+// Forward pass over all slices with the HS-field flips, stabilisation at
+// block ends (push (Q_k, V_k)), wrap check and measurements at interior
+// boundaries, and the fresh weight and inverse at tau = beta.
+__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, int mm, int do_measure) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  Lds L = carve(mm);
+  const int N = w.N, n = w.nblk;
+  const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
+  if (TID == 0) { L.scal[10] = 0.0; L.scal[11] = 1.0; }
+  for (int sp = 0; sp < 2; ++sp) fill_P(w, sp, w.PhiR[sp]);
+  double ld_tot = 0.0;
+  double maxwrap = 0.0;
+  for (int k = 1; k <= n; ++k) {
+    int fresh_sign = 1;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      double *Ms = sp ? L.Ms1 : L.Ms0;
+      copy_global(w.X[sp], w.LS[sp] + (size_t)(k - 1) * N * m, (size_t)N * m);
+      gram(w.X[sp], m, w.PhiR[sp], m, N, L.A, L.red);
+      double la;
+      int sg = 1;
+      if (m > 0) {
+        if (!gj_inverse(L.A, Ms, m, L, &la, &sg))
+          if (TID == 0) w.sc->status |= 4;
+      }
+      fresh_sign *= sg;
+      if (k > 1 && m > 0) {
+        // wrapped diagonal of A from the end of block k-1 vs the fresh one
+        double dmax = 0.0;
+        for (int i = TID; i < N; i += kThreads) {
+          double s = 0.0;
+          for (int p = 0; p < m; ++p) {
+            double acc = 0.0;
+            for (int q = 0; q < m; ++q) acc += Ms[p * m + q] * w.X[sp][(size_t)i * m + q];
+            s += w.PhiR[sp][(size_t)i * m + p] * acc;
+          }
+          dmax = fmax(dmax, fabs(s - w.Aw[sp][i]));
+        }
+        dmax = wg_max(dmax, L.red);
+        maxwrap = fmax(maxwrap, dmax);
+      }
+    }
+    if (k > 1 && do_measure) {
+      double *const PR[2] = {w.PhiR[0], w.PhiR[1]};
+      double *const XL[2] = {w.X[0], w.X[1]};
+      const double *Ms[2] = {L.Ms0, L.Ms1};
+      measure_point(w, PR, XL, Ms, fresh_sign, L);
+    }
+    const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
+    for (int l = l0; l <= l1; ++l) {
+      for (int sp = 0; sp < 2; ++sp) {
+        apply_diag(w, w.PhiR[sp], w.ne[sp], l, sp, false);
+        apply_diag(w, w.X[sp], w.ne[sp], l, sp, true);
+      }
+      if (!(w.flags & 2)) flip_slice(w, l, sweep, L);
+      for (int sp = 0; sp < 2; ++sp) {
+        apply_ek(w, w.PhiR[sp], w.ne[sp]);
+        apply_ekinvT(w, w.X[sp], w.ne[sp]);
+      }
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      const double *Ms = sp ? L.Ms1 : L.Ms0;
+      if (k < n && m > 0) {
+        for (int i = TID; i < N; i += kThreads) {
+          double s = 0.0;
+          for (int p = 0; p < m; ++p) {
+            double acc = 0.0;
+            for (int q = 0; q < m; ++q) acc += Ms[p * m + q] * w.X[sp][(size_t)i * m + q];
+            s += w.PhiR[sp][(size_t)i * m + p] * acc;
+          }
+          w.Aw[sp][i] = s;
+        }
+        SYNC();
+      }
+      double *Q = w.RQ[sp] + (size_t)(k - 1) * N * m;
+      double *V = w.RV[sp] + (size_t)(k - 1) * m * m;
+      ld_tot += cholqr(w.PhiR[sp], w.T[sp], Q, w.PhiR[sp], V, w.fVp, N, m, L, w.sc);
+    }
+  }
+  // tau = beta: inverse of P^T Q_n and the fresh weight
+  int sg_tot = 1;
+  for (int sp = 0; sp < 2; ++sp) {
+    double la;
+    int sg;
+    inverse_at_beta(w, sp, L, &la, &sg);
+    ld_tot += la;
+    sg_tot *= sg;
+  }
+  if (n == 1 && do_measure) {
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      fill_P(w, sp, w.X[sp]);
+      copy_global(w.PhiR[sp], w.RQ[sp], (size_t)N * m);
+      double *dst = sp ? L.Ms1 : L.Ms0;
+      for (int t = TID; t < m * m; t += kThreads) dst[t] = w.Minv[sp][t];
+      SYNC();
+    }
+    double *const PR[2] = {w.PhiR[0], w.PhiR[1]};
+    double *const XL[2] = {w.X[0], w.X[1]};
+    const double *Ms[2] = {L.Ms0, L.Ms1};
+    measure_point(w, PR, XL, Ms, sg_tot, L);
+  }
+  if (TID == 0) {
+    Scalars *sc = w.sc;
+    const double tracked = sc->logw + L.scal[10];
+    const double drift = fabs(tracked - ld_tot);
+    if (drift > sc->logw_drift) sc->logw_drift = drift;
+    if (maxwrap > sc->max_wrap) sc->max_wrap = maxwrap;
+    sc->logw = ld_tot;
+    sc->sign = sg_tot;
+    sc->fresh_logw = ld_tot;
+    sc->fresh_sign = sg_tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Particle-hole swap (removal of occupied index k, addition of site j).
+// Removal (SM Sec. I.B): permutation U moving column k last, then at each
+// level Givens rotations retriangulating V_1 U or V_i G_{i-1}^T; the last
+// diagonal gives r_Ne, and M_perm^{-1} = G_n M^{-1} U.  Addition (SM Sec. I.A)
+// on the reduced system: propagate e_j through each block, project out the
+// reduced basis twice (classical Gram-Schmidt, second pass for stability),
+// normalise.  Ratio r = [M_perm^{-1}]_{Ne,Ne} / r_Ne * s * prod_i rho_i.
+// LDS: Ms0 = Hessenberg work, Ms1 = M_perm^{-1}, A = reduced inverse.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int perm_col(int c, int k, int ne) {
+  return c < k ? c : (c < ne - 1 ? c + 1 : k);
+}
+
+// returns accepted (uniform); *log_abs_r / *sign_r in scal
+__device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc, bool commit,
+                          Lds &L, double *ratio_out) {
+  const int N = w.N, ne = w.ne[sp], m = ne - 1, n = w.nblk, mm = w.mmax;
+  double *H = L.Ms0, *Mp = L.Ms1, *Mred = L.A;
+  double *y = L.vec, *z = L.vec + 64, *vsum = L.vec + 128, *acol = L.vec + 192, *brow = L.vec + 256,
+         *tv = L.vec + 320;
+  // scal[20] log_rne, [21] sign_rne, [22] zero flag, [23] log_rho
+  if (TID == 0) { L.scal[20] = 0.0; L.scal[21] = 1.0; L.scal[22] = 0.0; L.scal[23] = 0.0; }
+  SYNC();
+  // ---- removal ----
+  for (int lvl = 0; lvl < n; ++lvl) {
+    const double *V = w.RV[sp] + (size_t)lvl * ne * ne;
+    if (lvl == 0) {
+      for (int t = TID; t < ne * ne; t += kThreads) {
+        const int r = t / ne, c = t % ne;
+        H[t] = V[r * ne + perm_col(c, k, ne)];
+      }
+      SYNC();
+    } else {
+      for (int t = TID; t < ne * ne; t += kThreads) H[t] = V[t];
+      SYNC();
+      const double *gc = w.fgc + (size_t)(lvl - 1) * mm, *gs = w.fgs + (size_t)(lvl - 1) * mm;
+      for (int r = k; r <= ne - 2; ++r) {
+        const double cc = gc[r], ss = gs[r];
+        for (int row = TID; row < ne; row += kThreads) {
+          const double a = H[row * ne + r], b = H[row * ne + r + 1];
+          H[row * ne + r] = cc * a + ss * b;
+          H[row * ne + r + 1] = -ss * a + cc * b;
+        }
+        SYNC();
+      }
+    }
+    double *gc = w.fgc + (size_t)lvl * mm, *gs = w.fgs + (size_t)lvl * mm;
+    for (int r = k; r <= ne - 2; ++r) {
+      if (TID == 0) {
+        const double a = H[r * ne + r], b = H[(r + 1) * ne + r];
+        const double hh = hypot(a, b);
+        double cc = 1.0, ss = 0.0;
+        if (hh != 0.0) { cc = a / hh; ss = b / hh; }
+        L.scal[24] = cc;
+        L.scal[25] = ss;
+        gc[r] = cc;
+        gs[r] = ss;
+      }
+      SYNC();
+      const double cc = L.scal[24], ss = L.scal[25];
+      for (int col = r + TID; col < ne; col += kThreads) {
+        const double u = H[r * ne + col], d = H[(r + 1) * ne + col];
+        H[r * ne + col] = cc * u + ss * d;
+        H[(r + 1) * ne + col] = -ss * u + cc * d;
+      }
+      SYNC();
+      if (TID == 0) H[(r + 1) * ne + r] = 0.0;
+    }
+    SYNC();
+    double *Vp = w.fVp + (size_t)lvl * mm * mm;
+    for (int t = TID; t < ne * ne; t += kThreads) Vp[t] = H[t];
+    if (TID == 0) {
+      const double last = H[(ne - 1) * ne + (ne - 1)];
+      L.scal[20] += log(fabs(last));
+      if (last < 0.0) L.scal[21] = -L.scal[21];
+      if (last == 0.0) L.scal[22] = 1.0;
+    }
+    SYNC();
+  }
+  // M_perm^{-1} = G_n M^{-1} U  (B as work)
+  {
+    double *Tm = L.B;
+    for (int t = TID; t < ne * ne; t += kThreads) Tm[t] = w.Minv[sp][t];
+    SYNC();
+    const double *gc = w.fgc + (size_t)(n - 1) * mm, *gs = w.fgs + (size_t)(n - 1) * mm;
+    for (int r = k; r <= ne - 2; ++r) {
+      const double cc = gc[r], ss = gs[r];
+      for (int col = TID; col < ne; col += kThreads) {
+        const double a = Tm[r * ne + col], b = Tm[(r + 1) * ne + col];
+        Tm[r * ne + col] = cc * a + ss * b;
+        Tm[(r + 1) * ne + col] = -ss * a + cc * b;
+      }
+      SYNC();
+    }
+    for (int t = TID; t < ne * ne; t += kThreads) {
+      const int r = t / ne, c = t % ne;
+      Mp[t] = Tm[r * ne + perm_col(c, k, ne)];
+    }
+    SYNC();
+  }
+  const double mlast = Mp[(ne - 1) * ne + (ne - 1)];
+  if (TID == 0 && mlast == 0.0) L.scal[22] = 1.0;
+  for (int t = TID; t < m * m; t += kThreads) {
+    const int a = t / m, b = t % m;
+    Mred[t] = Mp[a * ne + b] - Mp[a * ne + (ne - 1)] * Mp[(ne - 1) * ne + b] / mlast;
+  }
+  SYNC();
+  const double log_rem = log(fabs(mlast)) - L.scal[20];
+  const double sign_rem = (mlast < 0.0 ? -1.0 : 1.0) * L.scal[21];
+  // ---- addition ----
+  double *fw = w.fw;
+  if (L.scal[22] == 0.0) {
+    for (int i = TID; i < N; i += kThreads) fw[i] = (i == j) ? 1.0 : 0.0;
+    SYNC();
+    for (int lvl = 0; lvl < n; ++lvl) {
+      const int l0 = lvl * w.nstab + 1, l1 = min((lvl + 1) * w.nstab, w.L);
+      for (int l = l0; l <= l1; ++l) {
+        apply_diag(w, fw, 1, l, sp, false);
+        apply_ek(w, fw, 1);
+      }
+      const double *Q = w.RQ[sp] + (size_t)lvl * N * ne;
+      const double *gc = w.fgc + (size_t)lvl * mm, *gs = w.fgs + (size_t)lvl * mm;
+      for (int a = TID; a < 64; a += kThreads) vsum[a] = 0.0;
+      SYNC();
+      for (int pass = 0; pass < 2 && m > 0; ++pass) {
+        gram(Q, ne, fw, 1, N, y, L.red);  // y = Q^T w
+        if (TID == 0) {
+          for (int r = k; r <= ne - 2; ++r) {
+            const double a = y[r], b = y[r + 1];
+            y[r] = gc[r] * a + gs[r] * b;
+            y[r + 1] = -gs[r] * a + gc[r] * b;
+          }
+          for (int a = 0; a < ne; ++a) z[a] = a < m ? y[a] : 0.0;
+          for (int a = 0; a < m; ++a) vsum[a] += z[a];
+          for (int r = ne - 2; r >= k; --r) {
+            const double a = z[r], b = z[r + 1];
+            z[r] = gc[r] * a - gs[r] * b;
+            z[r + 1] = gs[r] * a + gc[r] * b;
+          }
+        }
+        SYNC();
+        for (int i = TID; i < N; i += kThreads) {
+          double s = 0.0;
+          for (int a = 0; a < ne; ++a) s += Q[(size_t)i * ne + a] * z[a];
+          fw[i] -= s;
+        }
+        SYNC();
+      }
+      double nrm = 0.0;
+      for (int i = TID; i < N; i += kThreads) nrm += fw[i] * fw[i];
+      nrm = sqrt(wg_sum(nrm, L.red));
+      if (!(nrm > 1e-300)) {
+        if (TID == 0) L.scal[22] = 1.0;
+        SYNC();
+        break;
+      }
+      double *q = w.fq + (size_t)lvl * N;
+      for (int i = TID; i < N; i += kThreads) {
+        const double v = fw[i] / nrm;
+        q[i] = v;
+        fw[i] = v;
+      }
+      if (TID == 0) {
+        for (int a = 0; a < m; ++a) w.fv[(size_t)lvl * mm + a] = vsum[a];
+        w.frho[lvl] = nrm;
+        L.scal[23] += log(nrm);
+      }
+      SYNC();
+    }
+  }
+  bool accepted = false;
+  double ratio = 0.0;
+  if (L.scal[22] == 0.0) {
+    const double *Qn = w.RQ[sp] + (size_t)(n - 1) * N * ne;
+    const double *qn = w.fq + (size_t)(n - 1) * N;
+    const int *occ = w.occ[sp];
+    if (TID == 0) {
+      const double *gc = w.fgc + (size_t)(n - 1) * mm, *gs = w.fgs + (size_t)(n - 1) * mm;
+      for (int a = 0; a < ne; ++a) tv[a] = Qn[(size_t)j * ne + a];
+      for (int r = k; r <= ne - 2; ++r) {
+        const double a = tv[r], b = tv[r + 1];
+        tv[r] = gc[r] * a + gs[r] * b;
+        tv[r + 1] = -gs[r] * a + gc[r] * b;
+      }
+    }
+    SYNC();
+    for (int a = TID; a < m; a += kThreads) {
+      double s = 0.0;
+      for (int b = 0; b < m; ++b) s += Mred[a * m + b] * qn[occ[perm_col(b, k, ne)]];
+      acol[a] = s;
+    }
+    for (int b = TID; b < m; b += kThreads) {
+      double s = 0.0;
+      for (int a = 0; a < m; ++a) s += tv[a] * Mred[a * m + b];
+      brow[b] = s;
+    }
+    SYNC();
+    if (TID == 0) {
+      double sch = qn[j];
+      for (int a = 0; a < m; ++a) sch -= tv[a] * acol[a];
+      L.scal[26] = sch;
+    }
+    SYNC();
+    const double sch = L.scal[26];
+    if (sch != 0.0) {
+      const double lr = log_rem + log(fabs(sch)) + L.scal[23];
+      const double sr = sign_rem * (sch < 0.0 ? -1.0 : 1.0);
+      ratio = sr * exp(lr);
+      accepted = xacc < exp(lr);
+      if (accepted && commit) {
+        for (int lvl = 0; lvl < n; ++lvl) {
+          double *Q = w.RQ[sp] + (size_t)lvl * N * ne;
+          const double *gc = w.fgc + (size_t)lvl * mm, *gs = w.fgs + (size_t)lvl * mm;
+          const double *q = w.fq + (size_t)lvl * N;
+          for (int i = TID; i < N; i += kThreads) {
+            double *row = Q + (size_t)i * ne;
+            for (int r = k; r <= ne - 2; ++r) {
+              const double a = row[r], b = row[r + 1];
+              row[r] = gc[r] * a + gs[r] * b;
+              row[r + 1] = -gs[r] * a + gc[r] * b;
+            }
+            row[ne - 1] = q[i];
+          }
+          double *V = w.RV[sp] + (size_t)lvl * ne * ne;
+          const double *Vp = w.fVp + (size_t)lvl * mm * mm;
+          for (int t = TID; t < ne * ne; t += kThreads) {
+            const int a = t / ne, b = t % ne;
+            double val = 0.0;
+            if (a < m && b < m) val = Vp[a * ne + b];
+            else if (b == ne - 1 && a < m) val = w.fv[(size_t)lvl * mm + a];
+            else if (a == ne - 1 && b == ne - 1) val = w.frho[lvl];
+            V[t] = val;
+          }
+        }
+        const double is = 1.0 / sch;
+        double *Mi = w.Minv[sp];
+        for (int t = TID; t < ne * ne; t += kThreads) {
+          const int a = t / ne, b = t % ne;
+          double val;
+          if (a < m && b < m) val = Mred[a * m + b] + is * acol[a] * brow[b];
+          else if (a < m) val = -is * acol[a];
+          else if (b < m) val = -is * brow[b];
+          else val = is;
+          Mi[t] = val;
+        }
+        int *nocc = L.iscal + 64;
+        for (int a = TID; a < m; a += kThreads) nocc[a] = occ[perm_col(a, k, ne)];
+        SYNC();
+        for (int a = TID; a < m; a += kThreads) w.occ[sp][a] = nocc[a];
+        if (TID == 0) {
+          w.occ[sp][ne - 1] = j;
+          w.sc->logw += lr;
+          w.sc->sign *= (int)sr;
+        }
+      }
+    }
+  }
+  SYNC();
+  if (ratio_out && TID == 0) *ratio_out = ratio;
+  return accepted;
+}
+
+// index of the nth empty site (ascending) of spin sp
+__device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
+  const int N = w.N, ne = w.ne[sp];
+  for (int i = TID; i < N; i += kThreads) w.fmark[i] = 0;
+  SYNC();
+  for (int a = TID; a < ne; a += kThreads) w.fmark[w.occ[sp][a]] = 1;
+  SYNC();
+  const int chunk = (N + kThreads - 1) / kThreads;
+  int cnt = 0;
+  for (int i = TID * chunk; i < min(N, (TID + 1) * chunk); ++i) cnt += w.fmark[i] == 0;
+  int *counts = L.iscal + 64;
+  counts[TID] = cnt;
+  SYNC();
+  if (TID == 0) {
+    int acc = 0, owner = 0;
+    for (int t = 0; t < kThreads; ++t) {
+      if (acc + counts[t] > nth) { owner = t; break; }
+      acc += counts[t];
+    }
+    int site = -1, c = acc;
+    for (int i = owner * chunk; i < min(N, (owner + 1) * chunk); ++i)
+      if (w.fmark[i] == 0) {
+        if (c == nth) { site = i; break; }
+        ++c;
+      }
+    L.iscal[3] = site;
+  }
+  SYNC();
+  const int s = L.iscal[3];
+  SYNC();
+  return s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, int mm) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  Lds L = carve(mm);
+  const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
+  if (!(w.flags & 1)) {
+    for (int sp = 0; sp < 2; ++sp) {
+      const int ne = w.ne[sp];
+      if (ne == 0 || ne == w.N) continue;
+      for (int t = 0; t < ne; ++t) {
+        const int k = pick(uniform01(w.seed, w.wid, kSwapK, sweep, (uint32_t)sp, (uint32_t)t), ne);
+        const int jn = pick(uniform01(w.seed, w.wid, kSwapJ, sweep, (uint32_t)sp, (uint32_t)t), w.N - ne);
+        const int j = nth_empty(w, sp, jn, L);
+        const double xacc = uniform01(w.seed, w.wid, kSwapAcc, sweep, (uint32_t)sp, (uint32_t)t);
+        const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, nullptr);
+        if (TID == 0) {
+          w.sc->swap_att += 1;
+          if (acc) w.sc->swap_acc += 1;
+        }
+        SYNC();
+      }
+    }
+  }
+  if (TID == 0) w.sc->sweep += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Parity surface
+// ---------------------------------------------------------------------------
+// stabilised right state B_b ... B_1 P (QR at multiples of n_stab and at b) in PhiR
+__device__ void right_state(const WalkerDesc &w, int sp, int b, Lds &L) {
+  const int m = w.ne[sp];
+  double *Phi = w.PhiR[sp];
+  fill_P(w, sp, Phi);
+  for (int l = 1; l <= b; ++l) {
+    apply_diag(w, Phi, m, l, sp, false);
+    apply_ek(w, Phi, m);
+    if (l % w.nstab == 0 || l == b) cholqr(Phi, w.T[sp], Phi, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
+  }
+}
+// stabilised left state (P^T B_L ... B_{b+1})^T in X
+__device__ void left_state(const WalkerDesc &w, int sp, int b, Lds &L) {
+  const int m = w.ne[sp];
+  double *Y = w.X[sp];
+  fill_P(w, sp, Y);
+  int cnt = 0;
+  for (int l = w.L; l > b; --l) {
+    apply_ekT(w, Y, m);
+    apply_diag(w, Y, m, l, sp, false);
+    if (++cnt % w.nstab == 0 || l == b + 1) cholqr(Y, w.T[sp], Y, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *descs, int mm, int b, int sp, double *G) {
+  const WalkerDesc &w = descs[0];
+  Lds L = carve(mm);
+  const int N = w.N, m = w.ne[sp];
+  right_state(w, sp, b, L);
+  left_state(w, sp, b, L);
+  gram(w.X[sp], m, w.PhiR[sp], m, N, L.A, L.red);
+  double la;
+  int sg;
+  if (m > 0) gj_inverse(L.A, L.B, m, L, &la, &sg);
+  // T = Phi_R M^{-1}
+  for (int t = TID; t < N * m; t += kThreads) {
+    const int i = t / m, c = t % m;
+    double s = 0.0;
+    for (int a = 0; a < m; ++a) s += w.PhiR[sp][(size_t)i * m + a] * L.B[a * m + c];
+    w.T[sp][t] = s;
+  }
+  SYNC();
+  for (size_t t = TID; t < (size_t)N * N; t += kThreads) {
+    const int i = (int)(t / N), jj = (int)(t % N);
+    double s = 0.0;
+    for (int c = 0; c < m; ++c) s += w.T[sp][(size_t)i * m + c] * w.X[sp][(size_t)jj * m + c];
+    G[t] = (i == jj ? 1.0 : 0.0) - s;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *descs, int mm, int slice, int site) {
+  const WalkerDesc &w = descs[0];
+  Lds L = carve(mm);
+  const int N = w.N, l = slice + 1;
+  double r = 1.0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    if (m == 0) continue;
+    right_state(w, sp, l - 1, L);
+    apply_diag(w, w.PhiR[sp], m, l, sp, false);
+    left_state(w, sp, l, L);
+    apply_ekT(w, w.X[sp], m);
+    gram(w.X[sp], m, w.PhiR[sp], m, N, L.A, L.red);
+    double la;
+    int sg;
+    gj_inverse(L.A, L.B, m, L, &la, &sg);
+    double a = 0.0;
+    if (TID == 0) {
+      for (int p = 0; p < m; ++p)
+        for (int q = 0; q < m; ++q)
+          a += w.PhiR[sp][(size_t)site * m + p] * L.B[p * m + q] * w.X[sp][(size_t)site * m + q];
+      const int ss = (sp == 0 ? 1 : -1) * w.s[(size_t)slice * N + site];
+      const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
+      r *= 1.0 + delta * a;
+    }
+    SYNC();
+  }
+  if (TID == 0) w.dbg[0] = r;
+}
+
+__global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *descs, int mm, int sp, int k, int j) {
+  const WalkerDesc &w = descs[0];
+  Lds L = carve(mm);
+  for (int s2 = 0; s2 < 2; ++s2) {
+    right_stack(w, s2, L);
+    double la;
+    int sg;
+    inverse_at_beta(w, s2, L, &la, &sg);
+  }
+  swap_move(w, sp, k, j, 2.0, false, L, w.dbg);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int clamp_mm(int mm) { return mm < 1 ? 1 : mm; }
+
+// allow dynamic LDS above the 64 KiB default for the large-Ne layouts
+template <typename K>
+static void lds_attr(K kernel, int mm) {
+  const size_t b = lds_bytes(mm);
+  if (b > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+hipError_t launch_init(const WalkerDesc *d, int draw_fields, int draw_occ, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(kThreads), 0, st, d, draw_fields, draw_occ);
+  return hipGetLastError();
+}
+hipError_t launch_fresh_weight(const WalkerDesc *d, int n, int mm, int set_tracked, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_fresh_weight, mm);
+  hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm, set_tracked);
+  return hipGetLastError();
+}
+hipError_t launch_left_stack(const WalkerDesc *d, int n, int mm, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_left_stack, mm);
+  hipLaunchKernelGGL(k_left_stack, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm);
+  return hipGetLastError();
+}
+hipError_t launch_forward(const WalkerDesc *d, int n, int mm, int do_measure, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_forward, mm);
+  hipLaunchKernelGGL(k_forward, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm, do_measure);
+  return hipGetLastError();
+}
+hipError_t launch_fock(const WalkerDesc *d, int n, int mm, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_fock, mm);
+  hipLaunchKernelGGL(k_fock, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm);
+  return hipGetLastError();
+}
+hipError_t launch_green(const WalkerDesc *d, int mm, int b, int sp, double *G, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_green, mm);
+  hipLaunchKernelGGL(k_green, dim3(1), dim3(kThreads), lds_bytes(mm), st, d, mm, b, sp, G);
+  return hipGetLastError();
+}
+hipError_t launch_flip_ratio(const WalkerDesc *d, int mm, int slice, int site, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_flip_ratio, mm);
+  hipLaunchKernelGGL(k_flip_ratio, dim3(1), dim3(kThreads), lds_bytes(mm), st, d, mm, slice, site);
+  return hipGetLastError();
+}
+hipError_t launch_swap_ratio(const WalkerDesc *d, int mm, int sp, int k, int j, hipStream_t st) {
+  mm = clamp_mm(mm);
+  lds_attr(k_swap_ratio, mm);
+  hipLaunchKernelGGL(k_swap_ratio, dim3(1), dim3(kThreads), lds_bytes(mm), st, d, mm, sp, k, j);
+  return hipGetLastError();
+}
+
+}  // namespace lecqmc
