@@ -102,7 +102,7 @@ int lecqmc_ctx_set_timing(lecqmc_ctx *ctx, int32_t enable);
 int lecqmc_ctx_phase_times(lecqmc_ctx *ctx, double ms[3], int64_t counts[3]);
 
 /* Device bytes one walker needs (right and left stacks dominate:
- * 2 * (2 n + 1) * N * Ne * 8 bytes); 0 if the input is invalid. */
+ * 2 * (2 n + 1 + L_tau) * N * Ne * 8 bytes); 0 if the input is invalid. */
 size_t lecqmc_footprint_bytes(const lecqmc_lattice *lat, const lecqmc_params *par);
 
 /* Create a walker: copies the lattice, builds the model tables, draws the

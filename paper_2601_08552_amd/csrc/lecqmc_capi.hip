@@ -74,6 +74,29 @@ struct lecqmc_walker {
 
 extern "C" const char *lecqmc_last_error(void) { return g_err; }
 
+// LDS residency per launch: a phase keeps its Slater blocks in LDS when the
+// largest walker of the launch fits next to the fixed layout.
+struct LaunchCfg {
+  int mm, phi_fwd, phi_left, phi_fock;
+};
+
+static int fit(int mm, long elems) {
+  return (elems > 0 && lds_bytes(mm, (int)elems) <= kLdsLimit) ? (int)elems : 0;
+}
+
+static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
+  int mm = 1;
+  long fwd = 0, left = 0, fock = 0;
+  for (int t = 0; t < n; ++t) {
+    const lecqmc_walker *w = ws[t];
+    mm = std::max(mm, w->mmax);
+    fwd = std::max(fwd, (long)w->N * (w->ne[0] + w->ne[1]));
+    left = std::max(left, (long)w->N * std::max(w->ne[0], w->ne[1]));
+    fock = std::max(fock, (long)w->N);
+  }
+  return {mm, fit(mm, fwd), fit(mm, left), fit(mm, fock)};
+}
+
 // ---------------------------------------------------------------------------
 // validation and memory plan
 // ---------------------------------------------------------------------------
@@ -120,7 +143,7 @@ static int validate(const lecqmc_lattice *lat, const lecqmc_params *par, int *L_
 }
 
 struct Plan {
-  size_t off_sc, off_desc, off_s, off_occ[2], off_LS[2], off_RQ[2], off_RV[2], off_Minv[2], off_PhiR[2], off_X[2],
+  size_t off_sc, off_desc, off_s, off_occ[2], off_LS[2], off_LX[2], off_RQ[2], off_RV[2], off_Minv[2], off_PhiR[2], off_X[2],
       off_T[2], off_Aw[2], off_fq, off_fw, off_fVp, off_fgc, off_fgs, off_fv, off_frho, off_fmark, off_obs,
       off_dbg, off_col, off_bi, off_bj, off_bdiag, off_boff, off_bh, off_epsf, off_eps, off_sub;
   size_t total;
@@ -144,6 +167,7 @@ static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int
   for (int s = 0; s < 2; ++s) {
     const size_t blk = (size_t)N * ne[s] * sizeof(double);
     p.off_LS[s] = take(blk * (nb + 1));
+    p.off_LX[s] = take(blk * L);
     p.off_RQ[s] = take(blk * nb);
     p.off_RV[s] = take(sizeof(double) * (size_t)ne[s] * ne[s] * nb);
     p.off_Minv[s] = take(sizeof(double) * (size_t)ne[s] * ne[s]);
@@ -323,6 +347,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   for (int s = 0; s < 2; ++s) {
     d.occ[s] = (int *)(base + p.off_occ[s]);
     d.LS[s] = (double *)(base + p.off_LS[s]);
+    d.LX[s] = (double *)(base + p.off_LX[s]);
     d.RQ[s] = (double *)(base + p.off_RQ[s]);
     d.RV[s] = (double *)(base + p.off_RV[s]);
     d.Minv[s] = (double *)(base + p.off_Minv[s]);
@@ -403,7 +428,8 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   if (e != hipSuccess) return cleanup(fail(LECQMC_EDEVICE, "upload: %s", hipGetErrorString(e)));
   const int draw_occ = (occ_up ? 0 : 1) | (occ_dn ? 0 : 2);
   if (!fields || draw_occ) e = launch_init(w->d_desc, fields ? 0 : 1, draw_occ, ctx->stream);
-  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, w->mmax, 1, ctx->stream);
+  const LaunchCfg cf = launch_cfg(&w, 1);
+  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, cf.mm, cf.phi_left, 1, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return cleanup(fail(LECQMC_EDEVICE, "init: %s", hipGetErrorString(e)));
   ctx->used += p.total;
@@ -430,10 +456,11 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
   HIPCHK(hipSetDevice(w->ctx->device));
   hipStream_t st = w->ctx->stream;
   lecqmc_ctx *c = w->ctx;
+  const LaunchCfg cf = launch_cfg(&w, 1);
   for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, w->mmax, st); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, w->mmax, do_measure, st); }));
-    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, w->mmax, st); }));
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.mm, cf.phi_left, st); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.mm, cf.phi_fwd, do_measure, st); }));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.mm, cf.phi_fock, st); }));
   }
   return 0;
 }
@@ -441,11 +468,9 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
 extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure) {
   if (!ws || n <= 0 || n_sweeps < 0) return fail(LECQMC_EINVAL, "bad arguments");
   lecqmc_ctx *c = ws[0]->ctx;
-  int mm = 1;
   std::vector<WalkerDesc> hd(n);
   for (int t = 0; t < n; ++t) {
     if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers of a batch must share one context");
-    mm = std::max(mm, ws[t]->mmax);
     hd[t] = ws[t]->h;
   }
   HIPCHK(hipSetDevice(c->device));
@@ -457,10 +482,11 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
+  const LaunchCfg cf = launch_cfg(ws, n);
   for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return launch_left_stack(c->d_batch, n, mm, c->stream); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(c->d_batch, n, mm, do_measure, c->stream); }));
-    HIPCHK(timed(c, 2, [&] { return launch_fock(c->d_batch, n, mm, c->stream); }));
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(c->d_batch, n, cf.mm, cf.phi_left, c->stream); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(c->d_batch, n, cf.mm, cf.phi_fwd, do_measure, c->stream); }));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(c->d_batch, n, cf.mm, cf.phi_fock, c->stream); }));
   }
   return 0;
 }
@@ -468,7 +494,8 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
 extern "C" int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign) {
   if (!w || !log_abs_w || !sign) return fail(LECQMC_EINVAL, "null argument");
   HIPCHK(hipSetDevice(w->ctx->device));
-  HIPCHK(launch_fresh_weight(w->d_desc, 1, w->mmax, 0, w->ctx->stream));
+  const LaunchCfg cf = launch_cfg(&w, 1);
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.mm, cf.phi_left, 0, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
   HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
@@ -564,7 +591,8 @@ extern "C" int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const in
   HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   sc.sweep = sweep_counter;
   HIPCHK(hipMemcpy(w->h.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
-  HIPCHK(launch_fresh_weight(w->d_desc, 1, w->mmax, 1, w->ctx->stream));
+  const LaunchCfg cf = launch_cfg(&w, 1);
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.mm, cf.phi_left, 1, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   return check_status(w);
 }

@@ -44,7 +44,8 @@ struct WalkerDesc {
   const int *sub;               // sublattice index
   int8_t *s;                    // [L][N]
   int *occ[2];                  // [N] each (first ne used)
-  double *LS[2];                // [(nblk + 1)][N][ne]
+  double *LS[2];                // [(nblk + 1)][N][ne]  left states at block boundaries
+  double *LX[2];                // [L][N][ne]  left state at the flip point of every slice
   double *RQ[2];                // [nblk][N][ne]
   double *RV[2];                // [nblk][ne][ne]
   double *Minv[2];              // [ne][ne]
@@ -64,15 +65,17 @@ struct WalkerDesc {
   Scalars *sc;
 };
 
-// kernel launchers (lecqmc_kernels.hip); descs = device array of descriptors
+// kernel launchers (lecqmc_kernels.hip); descs = device array of descriptors.
+// phi_elems > 0 keeps the Slater blocks of each walker resident in LDS.
+constexpr size_t kLdsLimit = 163840;
+size_t lds_bytes(int max_ne, int phi_elems);
 hipError_t launch_init(const WalkerDesc *d_desc, int draw_fields, int draw_occ, hipStream_t st);
-hipError_t launch_fresh_weight(const WalkerDesc *d_descs, int n, int max_ne, int set_tracked, hipStream_t st);
-hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, int max_ne, hipStream_t st);
-hipError_t launch_forward(const WalkerDesc *d_descs, int n, int max_ne, int do_measure, hipStream_t st);
-hipError_t launch_fock(const WalkerDesc *d_descs, int n, int max_ne, hipStream_t st);
+hipError_t launch_fresh_weight(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, int set_tracked, hipStream_t st);
+hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, hipStream_t st);
+hipError_t launch_forward(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, int do_measure, hipStream_t st);
+hipError_t launch_fock(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, hipStream_t st);
 hipError_t launch_green(const WalkerDesc *d_desc, int max_ne, int boundary, int spin, double *G, hipStream_t st);
 hipError_t launch_flip_ratio(const WalkerDesc *d_desc, int max_ne, int slice, int site, hipStream_t st);
 hipError_t launch_swap_ratio(const WalkerDesc *d_desc, int max_ne, int spin, int k, int j, hipStream_t st);
-size_t lds_bytes(int max_ne);
 
 }  // namespace lecqmc

@@ -46,40 +46,60 @@ __device__ __forceinline__ int pick(double u, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS layout (dynamic): sized by the largest Ne of the launch (mm).
+// LDS layout (dynamic): sized by the largest Ne of the launch (mm) and by the
+// Slater blocks kept resident in LDS (phi_elems doubles, 0 = streamed from
+// device memory through the staging buffers).
 // ---------------------------------------------------------------------------
 struct Lds {
   double *red;    // 256   block reductions
+  double *scal;   // 64    broadcast scalars
+  int *iscal;     // 320   broadcast integers + per-thread counts
   double *Ms0;    // mm^2  inverse, spin up   (Fock phase: Hessenberg work)
   double *Ms1;    // mm^2  inverse, spin down (Fock phase: permuted inverse)
   double *A;      // mm^2  Gram / Cholesky / pivot work (Fock phase: reduced inverse)
   double *B;      // mm^2  triangular inverse / output
-  double *uw;     // 2*64  flip-chain column vectors
   double *vec;    // 8*64  small vectors
-  double *scal;   // 64    broadcast scalars
-  int *iscal;     // 320   broadcast integers + per-thread counts
+  double *uw;     // 2*64  flip-chain column vectors (Ne > 32 path)
+  double *xs;     // [2 buf][2 spin][S][mm]  staged left rows
+  double *ps;     // [2 buf][2 spin][S][mm]  staged right rows (streamed mode)
+  double *us;     // [2 buf][S]              staged uniforms
+  int8_t *fs;     // [2 buf][S]              staged Ising fields
+  double *phi;    // resident Slater blocks, or nullptr
+  int S;          // sites per staged chunk
 };
 
-size_t lds_bytes(int mm) {
+__host__ __device__ inline int chunk_size(int mm) { return mm <= 16 ? 32 : (mm <= 32 ? 16 : 4); }
+
+size_t lds_bytes(int mm, int phi_elems) {
   if (mm < 1) mm = 1;
-  return sizeof(double) * (256 + 4 * (size_t)mm * mm + 2 * 64 + 8 * 64 + 64) + sizeof(int) * 320;
+  const size_t S = chunk_size(mm);
+  const size_t d = 256 + 64 + 4 * (size_t)mm * mm + 8 * 64 + 2 * 64 + 2 * (2 * 2 * S * mm) + 2 * S +
+                   (2 * S + 7) / 8 + (size_t)phi_elems;
+  return d * sizeof(double) + 320 * sizeof(int);
 }
 
 extern __shared__ double lds_raw[];
 
-__device__ Lds carve(int mm) {
+__device__ Lds carve(int mm, int phi_elems) {
   if (mm < 1) mm = 1;
+  const int S = chunk_size(mm);
   Lds L;
   double *p = lds_raw;
   L.red = p; p += 256;
+  L.scal = p; p += 64;
   L.Ms0 = p; p += mm * mm;
   L.Ms1 = p; p += mm * mm;
   L.A = p; p += mm * mm;
   L.B = p; p += mm * mm;
-  L.uw = p; p += 2 * 64;
   L.vec = p; p += 8 * 64;
-  L.scal = p; p += 64;
+  L.uw = p; p += 2 * 64;
+  L.xs = p; p += 2 * 2 * S * mm;
+  L.ps = p; p += 2 * 2 * S * mm;
+  L.us = p; p += 2 * S;
+  L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
+  L.phi = phi_elems > 0 ? p : nullptr; p += phi_elems;
   L.iscal = reinterpret_cast<int *>(p);
+  L.S = S;
   return L;
 }
 
@@ -371,91 +391,363 @@ __device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logab
 }
 
 // ---------------------------------------------------------------------------
-// Sequential Ising-flip chain over all sites of slice l (wave 0).
-// Lanes 0..31 carry spin up, lanes 32..63 spin down; lane h owns rows and
-// columns h and h + 32 of the spin's inverse (LDS).  Per site:
+// Cross-lane sums inside one 32-lane half of a wave64 (DPP and permlane).
+// Lane h = 8 ar + bc of a half.  sum_bc adds over bc (xor 1, xor 2, then the
+// other quad through the 8-lane half mirror); sum_ar adds over ar (xor 8 by a
+// rotate of 8 inside the 16-lane row, then the two 16-lane rows of the half
+// through permlane16_swap).  Every lane of a group ends with the bit-identical
+// sum, so decisions taken from it are uniform.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+__device__ __forceinline__ double swz16_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_ds_swizzle(hi, 0x401F), __builtin_amdgcn_ds_swizzle(lo, 0x401F));
+}
+__device__ __forceinline__ double sum_bc(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  return v;
+}
+__device__ __forceinline__ double sum_ar(double v) {
+  v += dpp_d<0x128>(v);  // row_ror:8
+  // permlane16_swap of a register with itself yields, in every lane, the
+  // value of the even 16-lane row of its pair of rows and that of the odd row
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+// (value of lane l & 31, value of lane (l & 31) + 32) for every lane l
+__device__ __forceinline__ double halves_product(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double lower = __hiloint2double((int)b[0], (int)a[0]);
+  const double upper = __hiloint2double((int)b[1], (int)a[1]);
+  return lower * upper;
+}
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Sequential Ising-flip chain over one staged chunk of sites (wave 0).
+// Lanes 0..31 carry spin up, lanes 32..63 spin down.  Per site i:
 //   a_s = Phi_R[i,:] M_s^{-1} Phi_L[:,i],  r_s = 1 + Delta_s a_s,  r = r_up r_dn,
 // accept if U(FLIP, sweep, l, i) < |r|; on acceptance the Sherman-Morrison
 // update M^{-1} -= (Delta/r)(M^{-1} Phi_L[:,i])(Phi_R[i,:] M^{-1}) and the row
-// scaling Phi_R[i,:] *= 1 + Delta.
+// scaling Phi_R[i,:] *= 1 + Delta (main text: fast update of the
+// auxiliary-field sweep, as in projector QMC).
+//
+// Register-tiled version for Ne <= 8T: lane (ar, bc) of a half holds rows
+// ar*2T .. ar*2T+2T-1 and columns bc*T .. bc*T+T-1 of its spin's inverse.
 // ---------------------------------------------------------------------------
-__device__ void flip_slice(const WalkerDesc &w, int l, uint32_t sweep, Lds &L) {
-  if (TID < 64) {
-    const int lane = TID, sp = lane >> 5, h = lane & 31;
-    const int m = w.ne[sp];
-    double *Ms = sp ? L.Ms1 : L.Ms0;
-    double *PR = w.PhiR[sp];
-    const double *XX = w.X[sp];
-    double *wsh = L.uw + sp * 64;
-    int8_t *srow = w.s + (size_t)(l - 1) * w.N;
-    double logw = 0.0;
-    int sgn = 1;
-    long long nacc = 0;
-    double xr = 0.0;
-    for (int i = 0; i < w.N; ++i) {
-      if ((i & 63) == 0) {
-        const int ii = i + lane;
-        xr = ii < w.N ? uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)ii) : 0.0;
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) int8_t lds_i8;
+__device__ __forceinline__ lds_f64 *as_lds(double *p) { return (lds_f64 *)p; }
+__device__ __forceinline__ const lds_f64 *as_lds(const double *p) { return (const lds_f64 *)p; }
+__device__ __forceinline__ lds_i8 *as_lds(int8_t *p) { return (lds_i8 *)p; }
+
+// log|W| bookkeeping of accepted flips: a mantissa product renormalised by
+// exponent bits (exact power-of-two scaling), logged once per block.
+struct ChainAcc {
+  double logw;
+  double prod;
+  int expo;
+  long long nacc;
+};
+__device__ __forceinline__ void acc_ratio(ChainAcc &acc, double r) {
+  if (r > 1e-300 && r < 1e300) {
+    const double pr = acc.prod * r;
+    int hi = __double2hiint(pr);
+    const int lo = __double2loint(pr);
+    acc.expo += ((hi >> 20) & 0x7ff) - 1022;
+    hi = (hi & 0x800fffff) | (1022 << 20);
+    acc.prod = __hiloint2double(hi, lo);
+  } else {
+    acc.logw += log(r);
+  }
+  acc.nacc += 1;
+}
+__device__ __forceinline__ double acc_total(const ChainAcc &acc) {
+  return acc.logw + log(acc.prod) + (double)acc.expo * 0.69314718055994530942;
+}
+
+template <int T>
+__device__ void chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], const double *xsb_g, int mm,
+                                double *prow_g, int ldp, const double *usb_g, int8_t *fsb_g, int cnt, int S,
+                                ChainAcc &acc) {
+  const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
+  const int m = w.ne[sp];
+  const lds_f64 *xsp = as_lds(xsb_g) + sp * S * mm;
+  lds_f64 *prow = as_lds(prow_g);
+  const lds_f64 *usb = as_lds(usb_g);
+  lds_i8 *fsb = as_lds(fsb_g);
+  const double dpos = w.delta_dn_s, dneg = w.delta_up_s;
+  double x[T], p[2 * T], xn[T], pn[2 * T];
+  int sv = 0, svn = 0;
+  double uv = 0.0, uvn = 0.0;
+  // staged left rows are zero-padded to mm columns; right-row reads are
+  // clamped to a valid column and masked, so every load is unconditional
+  int pcol[2 * T];
+  bool pon[2 * T];
+#pragma unroll
+  for (int i = 0; i < 2 * T; ++i) {
+    const int a = ar * 2 * T + i;
+    pcol[i] = a < m ? a : 0;
+    pon[i] = a < m;
+  }
+  auto load = [&](int r, double (&xx)[T], double (&pp)[2 * T], int &s_, double &u_) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) xx[j] = xsp[r * mm + bc * T + j];
+#pragma unroll
+    for (int i = 0; i < 2 * T; ++i) {
+      const double v = prow[r * ldp + pcol[i]];
+      pp[i] = pon[i] ? v : 0.0;
+    }
+    s_ = fsb[r];
+    u_ = usb[r];
+  };
+  if (cnt > 0) load(0, x, p, sv, uv);
+  for (int r = 0; r < cnt; ++r) {
+    if (r + 1 < cnt) load(r + 1, xn, pn, svn, uvn);
+    const int ss = sp == 0 ? sv : -sv;
+    const double delta = ss > 0 ? dpos : dneg;
+    double u[2 * T];
+    double ap = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2 * T; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < T; ++j) t += M[i][j] * x[j];
+      u[i] = sum_bc(t);
+      ap += p[i] * u[i];
+    }
+    const double a = sum_ar(ap);
+    double wv[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < 2 * T; ++i) t += p[i] * M[i][j];
+      wv[j] = sum_ar(t);
+    }
+    const double rsp = 1.0 + delta * a;
+    const double ratio = halves_product(rsp);
+    if (uv < fabs(ratio)) {
+      const double c = delta / rsp;
+#pragma unroll
+      for (int i = 0; i < 2 * T; ++i) {
+        const double cu = c * u[i];
+#pragma unroll
+        for (int j = 0; j < T; ++j) M[i][j] -= cu * wv[j];
       }
-      const double x = __shfl(xr, i & 63);
-      const int sv = srow[i];
-      const int ss = sp == 0 ? sv : -sv;
-      const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
-      const double *xrow = XX + (size_t)i * m;
-      double *prow = PR + (size_t)i * m;
-      double u0 = 0.0, u1 = 0.0, part = 0.0;
+      if (bc == 0) {
+#pragma unroll
+        for (int i = 0; i < 2 * T; ++i) {
+          const int aa = ar * 2 * T + i;
+          if (aa < m) prow[r * ldp + aa] = p[i] * (1.0 + delta);
+        }
+      }
+      if (lane == 0) fsb[r] = (int8_t)(-sv);
+      acc_ratio(acc, fabs(ratio));
+    }
+#pragma unroll
+    for (int j = 0; j < T; ++j) x[j] = xn[j];
+#pragma unroll
+    for (int i = 0; i < 2 * T; ++i) p[i] = pn[i];
+    sv = svn;
+    uv = uvn;
+  }
+}
+
+// LDS version for 32 < Ne <= 64: lane h of a half owns rows/columns h, h+32
+// of its spin's inverse, which stays in LDS (Ms0 / Ms1).
+__device__ void chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, int mm, double *prow, int ldp,
+                                const double *usb, int8_t *fsb, int cnt, int S, ChainAcc &acc) {
+  const int lane = TID & 63, sp = lane >> 5, h = lane & 31;
+  const int m = w.ne[sp];
+  double *Ms = sp ? L.Ms1 : L.Ms0;
+  double *wsh = L.uw + sp * 64;
+  const double *xsp = xsb + sp * S * mm;
+  for (int r = 0; r < cnt; ++r) {
+    const double *xrow = xsp + r * mm;
+    double *pr = prow + r * ldp;
+    const int sv = fsb[r];
+    const int ss = sp == 0 ? sv : -sv;
+    const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
+    double u0 = 0.0, u1 = 0.0, part = 0.0;
+    if (h < m) {
+      double t = 0.0;
+      for (int q = 0; q < m; ++q) t += Ms[h * m + q] * xrow[q];
+      u0 = t;
+      part += pr[h] * t;
+    }
+    if (h + 32 < m) {
+      double t = 0.0;
+      for (int q = 0; q < m; ++q) t += Ms[(h + 32) * m + q] * xrow[q];
+      u1 = t;
+      part += pr[h + 32] * t;
+    }
+    for (int o = 16; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+    const double rsp = 1.0 + delta * part;
+    const double ratio = lane_read(rsp, 0) * lane_read(rsp, 32);
+    if (usb[r] < fabs(ratio)) {
       if (h < m) {
-        double acc = 0.0;
-        for (int q = 0; q < m; ++q) acc += Ms[h * m + q] * xrow[q];
-        u0 = acc;
-        part += prow[h] * acc;
+        double t = 0.0;
+        for (int q = 0; q < m; ++q) t += pr[q] * Ms[q * m + h];
+        wsh[h] = t;
       }
       if (h + 32 < m) {
-        double acc = 0.0;
-        for (int q = 0; q < m; ++q) acc += Ms[(h + 32) * m + q] * xrow[q];
-        u1 = acc;
-        part += prow[h + 32] * acc;
+        double t = 0.0;
+        for (int q = 0; q < m; ++q) t += pr[q] * Ms[q * m + h + 32];
+        wsh[h + 32] = t;
       }
-      for (int o = 16; o >= 1; o >>= 1) part += __shfl_xor(part, o);
-      const double rsp = 1.0 + delta * part;
-      const double roth = __shfl_xor(rsp, 32);
-      const double ratio = sp == 0 ? rsp * roth : roth * rsp;
-      if (x < fabs(ratio)) {
-        if (h < m) {
-          double acc = 0.0;
-          for (int p = 0; p < m; ++p) acc += prow[p] * Ms[p * m + h];
-          wsh[h] = acc;
-        }
-        if (h + 32 < m) {
-          double acc = 0.0;
-          for (int p = 0; p < m; ++p) acc += prow[p] * Ms[p * m + h + 32];
-          wsh[h + 32] = acc;
-        }
-        wave_fence();
-        const double c = delta / rsp;
-        if (h < m) {
-          const double cu = c * u0;
-          for (int b = 0; b < m; ++b) Ms[h * m + b] -= cu * wsh[b];
-        }
-        if (h + 32 < m) {
-          const double cu = c * u1;
-          for (int b = 0; b < m; ++b) Ms[(h + 32) * m + b] -= cu * wsh[b];
-        }
-        wave_fence();
-        if (h < m) prow[h] *= 1.0 + delta;
-        if (h + 32 < m) prow[h + 32] *= 1.0 + delta;
-        if (lane == 0) srow[i] = (int8_t)(-sv);
-        logw += log(fabs(ratio));
-        if (ratio < 0.0) sgn = -sgn;
-        ++nacc;
-        wave_fence();
+      wave_fence();
+      const double c = delta / rsp;
+      if (h < m) {
+        const double cu = c * u0;
+        for (int b = 0; b < m; ++b) Ms[h * m + b] -= cu * wsh[b];
+      }
+      if (h + 32 < m) {
+        const double cu = c * u1;
+        for (int b = 0; b < m; ++b) Ms[(h + 32) * m + b] -= cu * wsh[b];
+      }
+      wave_fence();
+      if (h < m) pr[h] *= 1.0 + delta;
+      if (h + 32 < m) pr[h + 32] *= 1.0 + delta;
+      if (lane == 0) fsb[r] = (int8_t)(-sv);
+      acc_ratio(acc, fabs(ratio));
+      wave_fence();
+    }
+  }
+}
+
+// Stage chunk c (rows i0 .. i0+cnt-1) of slice l into buffer bufi: left rows
+// (Phi_L'^T = E_K^T Y_l, stored by the left-stack build), right rows when
+// streamed, fields and the flip uniforms.  Threads t0.. of the caller.
+__device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, int i0, int bufi,
+                            double *const phi[2], bool resident, int mm, int t0, int nt) {
+  if (TID < t0 || TID >= t0 + nt) return;
+  const int S = L.S, N = w.N;
+  const int cnt = min(S, N - i0);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    const double *lx = w.LX[sp] + (size_t)(l - 1) * N * m;
+    double *xd = L.xs + (size_t)(bufi * 2 + sp) * S * mm;
+    double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
+    for (int e = TID - t0; e < cnt * mm; e += nt) {
+      const int r = e / mm, a = e - (e / mm) * mm;
+      xd[e] = a < m ? lx[(size_t)(i0 + r) * m + a] : 0.0;
+      if (!resident && a < m) pd[e] = phi[sp][(size_t)(i0 + r) * m + a];
+    }
+  }
+  const int8_t *srow = w.s + (size_t)(l - 1) * N;
+  for (int r = TID - t0; r < cnt; r += nt) {
+    L.fs[bufi * S + r] = srow[i0 + r];
+    L.us[bufi * S + r] = uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)(i0 + r));
+  }
+}
+
+// Write back chunk rows modified by the chain (fields; right rows when streamed).
+__device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi, double *const phi[2],
+                            bool resident, int mm, int t0, int nt) {
+  if (TID < t0 || TID >= t0 + nt) return;
+  const int S = L.S, N = w.N;
+  const int cnt = min(S, N - i0);
+  if (!resident)
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      const double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
+      for (int e = TID - t0; e < cnt * m; e += nt) {
+        const int r = e / m, a = e - (e / m) * m;
+        phi[sp][(size_t)(i0 + r) * m + a] = pd[r * mm + a];
       }
     }
-    if (lane == 0) {
-      L.scal[10] += logw;
-      L.scal[11] *= (double)sgn;
-      w.sc->flip_att += w.N;
-      w.sc->flip_acc += nacc;
+  int8_t *srow = w.s + (size_t)(l - 1) * N;
+  for (int r = TID - t0; r < cnt; r += nt) srow[i0 + r] = L.fs[bufi * S + r];
+}
+
+// All slices of block k with the inverse held by wave 0.  On entry D_{l0} has
+// been applied and Ms0/Ms1 hold the fresh inverse at the flip point of l0;
+// on exit Ms0/Ms1 hold the updated inverse and phi = B_k ... applied.
+template <int T>
+__device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, double *const phi[2],
+                              bool resident, int mm, ChainAcc &acc) {
+  constexpr int TT = T > 0 ? T : 1;
+  const int N = w.N, S = L.S;
+  const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
+  const int nch = (N + S - 1) / S;
+  double M[2 * TT][TT];
+  const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
+  if constexpr (T > 0) {
+    if (TID < 64) {
+      const int m = w.ne[sp];
+      const double *Ms = sp ? L.Ms1 : L.Ms0;
+#pragma unroll
+      for (int i = 0; i < 2 * T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const int a = ar * 2 * T + i, b = bc * T + j;
+          M[i][j] = (a < m && b < m) ? Ms[a * m + b] : 0.0;
+        }
+    }
+  }
+  for (int l = l0; l <= l1; ++l) {
+    if (l > l0)
+      for (int s2 = 0; s2 < 2; ++s2) apply_diag(w, phi[s2], w.ne[s2], l, s2, false);
+    if (!(w.flags & 2)) {
+      stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
+      SYNC();
+      for (int c = 0; c < nch; ++c) {
+        const int bufi = c & 1, i0 = c * S;
+        const int cnt = min(S, N - i0);
+        if (TID < 64) {
+          const double *xsb = L.xs + (size_t)bufi * 2 * S * mm;
+          double *prow;
+          int ldp;
+          if (resident) {
+            prow = phi[sp] + (size_t)i0 * w.ne[sp];
+            ldp = w.ne[sp];
+          } else {
+            prow = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
+            ldp = mm;
+          }
+          if constexpr (T > 0)
+            chain_chunk_reg<T>(w, M, xsb, mm, prow, ldp, L.us + bufi * S, L.fs + bufi * S, cnt, S, acc);
+          else
+            chain_chunk_lds(w, L, xsb, mm, prow, ldp, L.us + bufi * S, L.fs + bufi * S, cnt, S, acc);
+        } else {
+          if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+          if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+        }
+        SYNC();
+      }
+      flush_chunk(w, L, l, (nch - 1) * S, (nch - 1) & 1, phi, resident, mm, 0, kThreads);
+      SYNC();
+    }
+    for (int s2 = 0; s2 < 2; ++s2) apply_ek(w, phi[s2], w.ne[s2]);
+  }
+  if constexpr (T > 0) {
+    if (TID < 64) {
+      const int m = w.ne[sp];
+      double *Ms = sp ? L.Ms1 : L.Ms0;
+#pragma unroll
+      for (int i = 0; i < 2 * T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const int a = ar * 2 * T + i, b = bc * T + j;
+          if (a < m && b < m) Ms[a * m + b] = M[i][j];
+        }
     }
   }
   SYNC();
@@ -466,7 +758,7 @@ __device__ void flip_slice(const WalkerDesc &w, int l, uint32_t sweep, Lds &L) {
 // boundary, accumulated sign-weighted in the observable layout of the ABI.
 // q = 0 sums use traces of Ne x Ne sublattice blocks, O(N Ne^2).
 // ---------------------------------------------------------------------------
-__device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *const XL[2],
+__device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR[2], double *const XL[2],
                               const double *Ms[2], int sgn, Lds &L) {
   const int N = w.N, ns = w.nsub;
   const double sg = (double)sgn;
@@ -482,10 +774,8 @@ __device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *
     }
   }
   SYNC();
-  // diagonal sums
+  // diagonal sums: A_ii per spin into T-adjacent scratch (Aw), then reductions
   double docc = 0.0, eon = 0.0, dens = 0.0;
-  double nsa[2][8];
-  for (int a = 0; a < 8; ++a) { nsa[0][a] = 0.0; nsa[1][a] = 0.0; }
   for (int i = TID; i < N; i += kThreads) {
     double ad[2];
     for (int sp = 0; sp < 2; ++sp) {
@@ -493,22 +783,25 @@ __device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *
       double s = 0.0;
       for (int b = 0; b < m; ++b) s += w.T[sp][(size_t)i * m + b] * XL[sp][(size_t)i * m + b];
       ad[sp] = s;
+      w.Aw[sp][i] = s;
     }
     docc += ad[0] * ad[1];
     eon += w.eps[i] * (ad[0] + ad[1]);
     dens += ad[0] + ad[1];
-    const int a = w.sub[i];
-    for (int q = 0; q < ns && q < 8; ++q)
-      if (q == a) { nsa[0][q] += ad[0]; nsa[1][q] += ad[1]; }
   }
   docc = wg_sum(docc, L.red);
   eon = wg_sum(eon, L.red);
   dens = wg_sum(dens, L.red);
-  double nup[8], ndn[8];
-  for (int a = 0; a < ns && a < 8; ++a) {
-    nup[a] = wg_sum(nsa[0][a], L.red);
-    ndn[a] = wg_sum(nsa[1][a], L.red);
-  }
+  // per-sublattice densities n_a^sigma (kept in LDS scalars 32..47)
+  for (int a = 0; a < ns; ++a)
+    for (int sp = 0; sp < 2; ++sp) {
+      double v = 0.0;
+      for (int i = TID; i < N; i += kThreads)
+        if (w.sub[i] == a) v += w.Aw[sp][i];
+      v = wg_sum(v, L.red);
+      if (TID == 0) L.scal[32 + 2 * a + sp] = v;
+    }
+  SYNC();
   // kinetic term: sum_b h_b (A_ij + A_ji) for both spins
   double ek = 0.0;
   for (int b = TID; b < w.nbonds; b += kThreads) {
@@ -541,10 +834,12 @@ __device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *
           tr += L.A[p * m + q] * L.B[q * m + p];
         }
         tr = wg_sum(tr, L.red);
-        const double na = sp == 0 ? nup[a] : ndn[a], nb = sp == 0 ? nup[b] : ndn[b];
+        const double na = L.scal[32 + 2 * a + sp], nb = L.scal[32 + 2 * b + sp];
         same[sp] = na * nb + (a == b ? na : 0.0) - tr;
       }
-      const double cross = nup[a] * ndn[b] + ndn[a] * nup[b];
+      const double nua = L.scal[32 + 2 * a], nda = L.scal[33 + 2 * a];
+      const double nub = L.scal[32 + 2 * b], ndb = L.scal[33 + 2 * b];
+      const double cross = nua * ndb + nda * nub;
       const double zz = 0.25 * (same[0] + same[1] - cross);
       // Z^a = sum_{i in a} X_up,i^T T_dn,i ; Z'^b = sum_{j in b} T_up,j^T X_dn,j
       gram(XL[0], mu, w.T[1], md, N, L.A, L.red, w.sub, a);
@@ -558,8 +853,8 @@ __device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *
       double d2 = 0.0;
       for (int t = TID; t < mu * md; t += kThreads) d2 += L.A[t] * L.B[t];
       d2 = wg_sum(d2, L.red);
-      const double pm = (a == b ? nup[a] : 0.0) - d1;
-      const double mp = (a == b ? ndn[a] : 0.0) - d2;
+      const double pm = (a == b ? nua : 0.0) - d1;
+      const double mp = (a == b ? nda : 0.0) - d2;
       const double xy = 0.5 * (pm + mp);
       if (TID == 0) {
         szz[a * ns + b] += sg * zz / w.ncells;
@@ -617,9 +912,8 @@ __device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *
 // Right chain from P with a QR at every block end; (Q_k, V_k) stored.
 // Returns sum_k sum_j log V_k,jj for spin sp.
 // ---------------------------------------------------------------------------
-__device__ double right_stack(const WalkerDesc &w, int sp, Lds &L) {
+__device__ double right_stack(const WalkerDesc &w, int sp, Lds &L, double *Phi) {
   const int m = w.ne[sp], N = w.N;
-  double *Phi = w.PhiR[sp];
   fill_P(w, sp, Phi);
   double ld = 0.0;
   for (int k = 1; k <= w.nblk; ++k) {
@@ -682,13 +976,15 @@ __global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *descs, int 
 }
 
 // Fresh log-weight from the current (eta, s): right stack + inverse at beta.
-__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *descs, int mm, int set_tracked) {
+__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *descs, int mm, int phi_elems,
+                                                           int set_tracked) {
   const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm);
+  Lds L = carve(mm, phi_elems);
   double la = 0.0;
   int sg = 1;
   for (int sp = 0; sp < 2; ++sp) {
-    la += right_stack(w, sp, L);
+    double *Phi = L.phi ? L.phi : w.PhiR[sp];
+    la += right_stack(w, sp, L, Phi);
     double l2;
     int s2;
     inverse_at_beta(w, sp, L, &l2, &s2);
@@ -702,21 +998,24 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *des
   }
 }
 
-// Left stack: Y <- P; for k = n..1: Y <- D_l E_K^T Y over the block's slices
-// (last to first), thin QR, LS[k-1] = Q.  LS[n] = P.
-__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs, int mm) {
+// Left stack, built backward from tau = beta: Y <- P; for slices l = L..1:
+// Y <- E_K^T Y, store X'_l = Y (the left state at the flip point of slice l,
+// (Phi_L(l) E_K)^T), Y <- D_l Y; at every block boundary a thin QR, LS[k-1] = Q.
+// LS[n] = P.  Y stays in LDS when it fits.
+__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs, int mm, int phi_elems) {
   const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm);
+  Lds L = carve(mm, phi_elems);
   const int N = w.N;
   for (int sp = 0; sp < 2; ++sp) {
     const int m = w.ne[sp];
-    double *Y = w.X[sp];
+    double *Y = L.phi ? L.phi : w.X[sp];
     fill_P(w, sp, Y);
     copy_global(w.LS[sp] + (size_t)w.nblk * N * m, Y, (size_t)N * m);
     for (int k = w.nblk; k >= 1; --k) {
       const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
       for (int l = l1; l >= l0; --l) {
         apply_ekT(w, Y, m);
+        copy_global(w.LX[sp] + (size_t)(l - 1) * N * m, Y, (size_t)N * m);
         apply_diag(w, Y, m, l, sp, false);
       }
       double *Q = w.LS[sp] + (size_t)(k - 1) * N * m;
@@ -728,81 +1027,93 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs
 // Forward pass over all slices with the HS-field flips, stabilisation at
 // block ends (push (Q_k, V_k)), wrap check and measurements at interior
 // boundaries, and the fresh weight and inverse at tau = beta.
-__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, int mm, int do_measure) {
+__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, int mm, int phi_elems, int do_measure) {
   const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm);
+  Lds L = carve(mm, phi_elems);
   const int N = w.N, n = w.nblk;
+  const bool resident = L.phi != nullptr;
   const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
-  if (TID == 0) { L.scal[10] = 0.0; L.scal[11] = 1.0; }
-  for (int sp = 0; sp < 2; ++sp) fill_P(w, sp, w.PhiR[sp]);
+  double *const phi[2] = {resident ? L.phi : w.PhiR[0], resident ? L.phi + (size_t)N * w.ne[0] : w.PhiR[1]};
+  const int mx = max(w.ne[0], w.ne[1]);
+  const int tsel = mx <= 8 ? 1 : (mx <= 16 ? 2 : (mx <= 32 ? 4 : 0));
+  ChainAcc acc{0.0, 1.0, 0, 0};
+  for (int sp = 0; sp < 2; ++sp) fill_P(w, sp, phi[sp]);
   double ld_tot = 0.0;
   double maxwrap = 0.0;
   for (int k = 1; k <= n; ++k) {
-    int fresh_sign = 1;
+    const int l0 = (k - 1) * w.nstab + 1;
+    // fresh inverse at the flip point of the block's first slice
     for (int sp = 0; sp < 2; ++sp) {
       const int m = w.ne[sp];
-      double *Ms = sp ? L.Ms1 : L.Ms0;
-      copy_global(w.X[sp], w.LS[sp] + (size_t)(k - 1) * N * m, (size_t)N * m);
-      gram(w.X[sp], m, w.PhiR[sp], m, N, L.A, L.red);
+      apply_diag(w, phi[sp], m, l0, sp, false);
+      gram(w.LX[sp] + (size_t)(l0 - 1) * N * m, m, phi[sp], m, N, L.A, L.red);
       double la;
-      int sg = 1;
-      if (m > 0) {
-        if (!gj_inverse(L.A, Ms, m, L, &la, &sg))
-          if (TID == 0) w.sc->status |= 4;
-      }
-      fresh_sign *= sg;
-      if (k > 1 && m > 0) {
-        // wrapped diagonal of A from the end of block k-1 vs the fresh one
-        double dmax = 0.0;
+      int sg;
+      if (m > 0 && !gj_inverse(L.A, sp ? L.Ms1 : L.Ms0, m, L, &la, &sg))
+        if (TID == 0) w.sc->status |= 4;
+    }
+    switch (tsel) {
+      case 1: forward_block<1>(w, k, sweep, L, phi, resident, mm, acc); break;
+      case 2: forward_block<2>(w, k, sweep, L, phi, resident, mm, acc); break;
+      case 4: forward_block<4>(w, k, sweep, L, phi, resident, mm, acc); break;
+      default: forward_block<0>(w, k, sweep, L, phi, resident, mm, acc); break;
+    }
+    // block end: diagonal of A with the updated inverse, kept for the wrap check
+    if (k < n)
+      for (int sp = 0; sp < 2; ++sp) {
+        const int m = w.ne[sp];
+        const double *Ms = sp ? L.Ms1 : L.Ms0;
+        const double *Xb = w.LS[sp] + (size_t)k * N * m;
         for (int i = TID; i < N; i += kThreads) {
           double s = 0.0;
           for (int p = 0; p < m; ++p) {
-            double acc = 0.0;
-            for (int q = 0; q < m; ++q) acc += Ms[p * m + q] * w.X[sp][(size_t)i * m + q];
-            s += w.PhiR[sp][(size_t)i * m + p] * acc;
-          }
-          dmax = fmax(dmax, fabs(s - w.Aw[sp][i]));
-        }
-        dmax = wg_max(dmax, L.red);
-        maxwrap = fmax(maxwrap, dmax);
-      }
-    }
-    if (k > 1 && do_measure) {
-      double *const PR[2] = {w.PhiR[0], w.PhiR[1]};
-      double *const XL[2] = {w.X[0], w.X[1]};
-      const double *Ms[2] = {L.Ms0, L.Ms1};
-      measure_point(w, PR, XL, Ms, fresh_sign, L);
-    }
-    const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
-    for (int l = l0; l <= l1; ++l) {
-      for (int sp = 0; sp < 2; ++sp) {
-        apply_diag(w, w.PhiR[sp], w.ne[sp], l, sp, false);
-        apply_diag(w, w.X[sp], w.ne[sp], l, sp, true);
-      }
-      if (!(w.flags & 2)) flip_slice(w, l, sweep, L);
-      for (int sp = 0; sp < 2; ++sp) {
-        apply_ek(w, w.PhiR[sp], w.ne[sp]);
-        apply_ekinvT(w, w.X[sp], w.ne[sp]);
-      }
-    }
-    for (int sp = 0; sp < 2; ++sp) {
-      const int m = w.ne[sp];
-      const double *Ms = sp ? L.Ms1 : L.Ms0;
-      if (k < n && m > 0) {
-        for (int i = TID; i < N; i += kThreads) {
-          double s = 0.0;
-          for (int p = 0; p < m; ++p) {
-            double acc = 0.0;
-            for (int q = 0; q < m; ++q) acc += Ms[p * m + q] * w.X[sp][(size_t)i * m + q];
-            s += w.PhiR[sp][(size_t)i * m + p] * acc;
+            double t = 0.0;
+            for (int q = 0; q < m; ++q) t += Ms[p * m + q] * Xb[(size_t)i * m + q];
+            s += phi[sp][(size_t)i * m + p] * t;
           }
           w.Aw[sp][i] = s;
         }
         SYNC();
       }
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
       double *Q = w.RQ[sp] + (size_t)(k - 1) * N * m;
       double *V = w.RV[sp] + (size_t)(k - 1) * m * m;
-      ld_tot += cholqr(w.PhiR[sp], w.T[sp], Q, w.PhiR[sp], V, w.fVp, N, m, L, w.sc);
+      ld_tot += cholqr(phi[sp], w.T[sp], Q, phi[sp], V, w.fVp, N, m, L, w.sc);
+    }
+    if (k < n) {
+      // fresh boundary quantities: Phi_R = Q_k, Phi_L = LS[k]^T
+      int fresh_sign = 1;
+      for (int sp = 0; sp < 2; ++sp) {
+        const int m = w.ne[sp];
+        double *Ms = sp ? L.Ms1 : L.Ms0;
+        const double *Xb = w.LS[sp] + (size_t)k * N * m;
+        gram(Xb, m, phi[sp], m, N, L.A, L.red);
+        double la;
+        int sg = 1;
+        if (m > 0) {
+          if (!gj_inverse(L.A, Ms, m, L, &la, &sg))
+            if (TID == 0) w.sc->status |= 4;
+          double dmax = 0.0;
+          for (int i = TID; i < N; i += kThreads) {
+            double s = 0.0;
+            for (int p = 0; p < m; ++p) {
+              double t = 0.0;
+              for (int q = 0; q < m; ++q) t += Ms[p * m + q] * Xb[(size_t)i * m + q];
+              s += phi[sp][(size_t)i * m + p] * t;
+            }
+            dmax = fmax(dmax, fabs(s - w.Aw[sp][i]));
+          }
+          dmax = wg_max(dmax, L.red);
+          maxwrap = fmax(maxwrap, dmax);
+        }
+        fresh_sign *= sg;
+      }
+      if (do_measure) {
+        double *const XL[2] = {w.LS[0] + (size_t)k * N * w.ne[0], w.LS[1] + (size_t)k * N * w.ne[1]};
+        const double *Ms[2] = {L.Ms0, L.Ms1};
+        measure_point(w, phi, XL, Ms, fresh_sign, L);
+      }
     }
   }
   // tau = beta: inverse of P^T Q_n and the fresh weight
@@ -818,19 +1129,17 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, i
     for (int sp = 0; sp < 2; ++sp) {
       const int m = w.ne[sp];
       fill_P(w, sp, w.X[sp]);
-      copy_global(w.PhiR[sp], w.RQ[sp], (size_t)N * m);
       double *dst = sp ? L.Ms1 : L.Ms0;
       for (int t = TID; t < m * m; t += kThreads) dst[t] = w.Minv[sp][t];
       SYNC();
     }
-    double *const PR[2] = {w.PhiR[0], w.PhiR[1]};
     double *const XL[2] = {w.X[0], w.X[1]};
     const double *Ms[2] = {L.Ms0, L.Ms1};
-    measure_point(w, PR, XL, Ms, sg_tot, L);
+    measure_point(w, phi, XL, Ms, sg_tot, L);
   }
   if (TID == 0) {
     Scalars *sc = w.sc;
-    const double tracked = sc->logw + L.scal[10];
+    const double tracked = sc->logw + acc_total(acc);
     const double drift = fabs(tracked - ld_tot);
     if (drift > sc->logw_drift) sc->logw_drift = drift;
     if (maxwrap > sc->max_wrap) sc->max_wrap = maxwrap;
@@ -838,6 +1147,8 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, i
     sc->sign = sg_tot;
     sc->fresh_logw = ld_tot;
     sc->fresh_sign = sg_tot;
+    if (!(w.flags & 2)) sc->flip_att += (long long)w.N * w.L;
+    sc->flip_acc += acc.nacc;
   }
 }
 
@@ -857,7 +1168,7 @@ __device__ __forceinline__ int perm_col(int c, int k, int ne) {
 
 // returns accepted (uniform); *log_abs_r / *sign_r in scal
 __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc, bool commit,
-                          Lds &L, double *ratio_out) {
+                          Lds &L, double *fw, double *ratio_out) {
   const int N = w.N, ne = w.ne[sp], m = ne - 1, n = w.nblk, mm = w.mmax;
   double *H = L.Ms0, *Mp = L.Ms1, *Mred = L.A;
   double *y = L.vec, *z = L.vec + 64, *vsum = L.vec + 128, *acol = L.vec + 192, *brow = L.vec + 256,
@@ -952,7 +1263,6 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
   const double log_rem = log(fabs(mlast)) - L.scal[20];
   const double sign_rem = (mlast < 0.0 ? -1.0 : 1.0) * L.scal[21];
   // ---- addition ----
-  double *fw = w.fw;
   if (L.scal[22] == 0.0) {
     for (int i = TID; i < N; i += kThreads) fw[i] = (i == j) ? 1.0 : 0.0;
     SYNC();
@@ -1137,9 +1447,10 @@ __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
   return s;
 }
 
-__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, int mm) {
+__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, int mm, int phi_elems) {
   const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm);
+  Lds L = carve(mm, phi_elems);
+  double *fw = (L.phi && phi_elems >= w.N) ? L.phi : w.fw;
   const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
   if (!(w.flags & 1)) {
     for (int sp = 0; sp < 2; ++sp) {
@@ -1150,7 +1461,7 @@ __global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, int 
         const int jn = pick(uniform01(w.seed, w.wid, kSwapJ, sweep, (uint32_t)sp, (uint32_t)t), w.N - ne);
         const int j = nth_empty(w, sp, jn, L);
         const double xacc = uniform01(w.seed, w.wid, kSwapAcc, sweep, (uint32_t)sp, (uint32_t)t);
-        const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, nullptr);
+        const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, fw, nullptr);
         if (TID == 0) {
           w.sc->swap_att += 1;
           if (acc) w.sc->swap_acc += 1;
@@ -1191,7 +1502,7 @@ __device__ void left_state(const WalkerDesc &w, int sp, int b, Lds &L) {
 
 __global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *descs, int mm, int b, int sp, double *G) {
   const WalkerDesc &w = descs[0];
-  Lds L = carve(mm);
+  Lds L = carve(mm, 0);
   const int N = w.N, m = w.ne[sp];
   right_state(w, sp, b, L);
   left_state(w, sp, b, L);
@@ -1217,7 +1528,7 @@ __global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *descs, int
 
 __global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *descs, int mm, int slice, int site) {
   const WalkerDesc &w = descs[0];
-  Lds L = carve(mm);
+  Lds L = carve(mm, 0);
   const int N = w.N, l = slice + 1;
   double r = 1.0;
   for (int sp = 0; sp < 2; ++sp) {
@@ -1247,14 +1558,14 @@ __global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *descs
 
 __global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *descs, int mm, int sp, int k, int j) {
   const WalkerDesc &w = descs[0];
-  Lds L = carve(mm);
+  Lds L = carve(mm, 0);
   for (int s2 = 0; s2 < 2; ++s2) {
-    right_stack(w, s2, L);
+    right_stack(w, s2, L, w.PhiR[s2]);
     double la;
     int sg;
     inverse_at_beta(w, s2, L, &la, &sg);
   }
-  swap_move(w, sp, k, j, 2.0, false, L, w.dbg);
+  swap_move(w, sp, k, j, 2.0, false, L, w.fw, w.dbg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1262,57 +1573,63 @@ __global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *descs
 // ---------------------------------------------------------------------------
 static int clamp_mm(int mm) { return mm < 1 ? 1 : mm; }
 
-// allow dynamic LDS above the 64 KiB default for the large-Ne layouts
+// allow dynamic LDS above the 64 KiB default
 template <typename K>
-static void lds_attr(K kernel, int mm) {
-  const size_t b = lds_bytes(mm);
-  if (b > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+static void lds_attr(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_init(const WalkerDesc *d, int draw_fields, int draw_occ, hipStream_t st) {
   hipLaunchKernelGGL(k_init, dim3(1), dim3(kThreads), 0, st, d, draw_fields, draw_occ);
   return hipGetLastError();
 }
-hipError_t launch_fresh_weight(const WalkerDesc *d, int n, int mm, int set_tracked, hipStream_t st) {
+hipError_t launch_fresh_weight(const WalkerDesc *d, int n, int mm, int phi_elems, int set_tracked, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_fresh_weight, mm);
-  hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm, set_tracked);
+  const size_t b = lds_bytes(mm, phi_elems);
+  lds_attr(k_fresh_weight, b);
+  hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems, set_tracked);
   return hipGetLastError();
 }
-hipError_t launch_left_stack(const WalkerDesc *d, int n, int mm, hipStream_t st) {
+hipError_t launch_left_stack(const WalkerDesc *d, int n, int mm, int phi_elems, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_left_stack, mm);
-  hipLaunchKernelGGL(k_left_stack, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm);
+  const size_t b = lds_bytes(mm, phi_elems);
+  lds_attr(k_left_stack, b);
+  hipLaunchKernelGGL(k_left_stack, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems);
   return hipGetLastError();
 }
-hipError_t launch_forward(const WalkerDesc *d, int n, int mm, int do_measure, hipStream_t st) {
+hipError_t launch_forward(const WalkerDesc *d, int n, int mm, int phi_elems, int do_measure, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_forward, mm);
-  hipLaunchKernelGGL(k_forward, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm, do_measure);
+  const size_t b = lds_bytes(mm, phi_elems);
+  lds_attr(k_forward, b);
+  hipLaunchKernelGGL(k_forward, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems, do_measure);
   return hipGetLastError();
 }
-hipError_t launch_fock(const WalkerDesc *d, int n, int mm, hipStream_t st) {
+hipError_t launch_fock(const WalkerDesc *d, int n, int mm, int phi_elems, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_fock, mm);
-  hipLaunchKernelGGL(k_fock, dim3(n), dim3(kThreads), lds_bytes(mm), st, d, mm);
+  const size_t b = lds_bytes(mm, phi_elems);
+  lds_attr(k_fock, b);
+  hipLaunchKernelGGL(k_fock, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems);
   return hipGetLastError();
 }
 hipError_t launch_green(const WalkerDesc *d, int mm, int b, int sp, double *G, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_green, mm);
-  hipLaunchKernelGGL(k_green, dim3(1), dim3(kThreads), lds_bytes(mm), st, d, mm, b, sp, G);
+  const size_t by = lds_bytes(mm, 0);
+  lds_attr(k_green, by);
+  hipLaunchKernelGGL(k_green, dim3(1), dim3(kThreads), by, st, d, mm, b, sp, G);
   return hipGetLastError();
 }
 hipError_t launch_flip_ratio(const WalkerDesc *d, int mm, int slice, int site, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_flip_ratio, mm);
-  hipLaunchKernelGGL(k_flip_ratio, dim3(1), dim3(kThreads), lds_bytes(mm), st, d, mm, slice, site);
+  const size_t by = lds_bytes(mm, 0);
+  lds_attr(k_flip_ratio, by);
+  hipLaunchKernelGGL(k_flip_ratio, dim3(1), dim3(kThreads), by, st, d, mm, slice, site);
   return hipGetLastError();
 }
 hipError_t launch_swap_ratio(const WalkerDesc *d, int mm, int sp, int k, int j, hipStream_t st) {
   mm = clamp_mm(mm);
-  lds_attr(k_swap_ratio, mm);
-  hipLaunchKernelGGL(k_swap_ratio, dim3(1), dim3(kThreads), lds_bytes(mm), st, d, mm, sp, k, j);
+  const size_t by = lds_bytes(mm, 0);
+  lds_attr(k_swap_ratio, by);
+  hipLaunchKernelGGL(k_swap_ratio, dim3(1), dim3(kThreads), by, st, d, mm, sp, k, j);
   return hipGetLastError();
 }
 

@@ -30,8 +30,9 @@ def test_library_exports_every_declared_symbol():
 def test_footprint_plan_scales_with_stacks():
     lat, par = W.config_dilute()
     fb = lecqmc.footprint_bytes(lat, par)
-    nblk = 32
-    stacks = 2 * (2 * nblk + 1) * 1024 * 8 * 8
+    nblk, L = 32, 320
+    # per spin: left states at boundaries (n+1) and at every slice (L), right stack (n)
+    stacks = 2 * (2 * nblk + 1 + L) * 1024 * 8 * 8
     assert stacks < fb < stacks * 1.3
 
 
