@@ -74,27 +74,45 @@ struct lecqmc_walker {
 
 extern "C" const char *lecqmc_last_error(void) { return g_err; }
 
-// LDS residency per launch: a phase keeps its Slater blocks in LDS when the
-// largest walker of the launch fits next to the fixed layout.
+// LDS plan per launch: a phase keeps its Slater blocks (then the compact bond
+// tables) in LDS when the largest walker of the launch fits next to the
+// fixed layout.
 struct LaunchCfg {
-  int mm, phi_fwd, phi_left, phi_fock;
+  LdsPlan fwd, left, fock, meas;
+  int slots;
 };
 
-static int fit(int mm, long elems) {
-  return (elems > 0 && lds_bytes(mm, (int)elems) <= kLdsLimit) ? (int)elems : 0;
+static LdsPlan plan_for(int mm, long phi_need, int bond_need, bool staged_if_streamed) {
+  LdsPlan p{mm, 0, 0, 0};
+  p.phi_elems = (int)phi_need;
+  if (phi_need <= 0 || lds_bytes(p) > kLdsLimit) {
+    p.phi_elems = 0;
+    p.stage_ps = staged_if_streamed ? 1 : 0;
+  }
+  if (bond_need > 0) {
+    p.bond_words = bond_need;
+    if (lds_bytes(p) > kLdsLimit) p.bond_words = 0;
+  }
+  return p;
 }
 
 static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
-  int mm = 1;
+  int mm = 1, bonds = 0, slots = 1;
   long fwd = 0, left = 0, fock = 0;
+  bool compact = true;
   for (int t = 0; t < n; ++t) {
     const lecqmc_walker *w = ws[t];
     mm = std::max(mm, w->mmax);
     fwd = std::max(fwd, (long)w->N * (w->ne[0] + w->ne[1]));
     left = std::max(left, (long)w->N * std::max(w->ne[0], w->ne[1]));
     fock = std::max(fock, (long)w->N);
+    if (w->h.ncoef == 0) compact = false;
+    bonds = std::max(bonds, w->h.bond_words);
+    slots = std::max(slots, w->nblk - 1);
   }
-  return {mm, fit(mm, fwd), fit(mm, left), fit(mm, fock)};
+  if (!compact) bonds = 0;
+  return {plan_for(mm, fwd, bonds, true), plan_for(mm, left, bonds, false), plan_for(mm, fock, bonds, false),
+          LdsPlan{mm, 0, 0, 0}, slots};
 }
 
 // ---------------------------------------------------------------------------
@@ -144,10 +162,17 @@ static int validate(const lecqmc_lattice *lat, const lecqmc_params *par, int *L_
 
 struct Plan {
   size_t off_sc, off_desc, off_s, off_occ[2], off_LS[2], off_LX[2], off_RQ[2], off_RV[2], off_Minv[2], off_PhiR[2], off_X[2],
-      off_T[2], off_Aw[2], off_fq, off_fw, off_fVp, off_fgc, off_fgs, off_fv, off_frho, off_fmark, off_obs,
-      off_dbg, off_col, off_bi, off_bj, off_bdiag, off_boff, off_bh, off_epsf, off_eps, off_sub;
+      off_T[2], off_Aw[2], off_mpart, off_mscr, off_fq, off_fw, off_fVp, off_fgc, off_fgs, off_fv, off_frho, off_fmark, off_obs,
+      off_dbg, off_col, off_bi, off_bj, off_bdiag, off_boff, off_bh, off_epsf, off_eps, off_sub, off_bij, off_bci,
+      off_coef;
+  size_t mscr_stride;
   size_t total;
 };
+
+// per-boundary measurement scratch: T (2 N mmax), diagonals (2 N), all-pair A (2 N^2 if N <= 64)
+static size_t meas_stride(int N, int mmax) {
+  return 2 * (size_t)N * mmax + 2 * (size_t)N + (N <= 64 ? 2 * (size_t)N * N : 0);
+}
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -174,16 +199,22 @@ static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int
     p.off_PhiR[s] = take(blk);
     p.off_X[s] = take(blk);
     p.off_T[s] = take(blk);
-    p.off_Aw[s] = take(sizeof(double) * N);
+    p.off_Aw[s] = take(sizeof(double) * (size_t)nb * N);
   }
-  p.off_fq = take(sizeof(double) * (size_t)nb * N);
-  p.off_fw = take(sizeof(double) * N);
-  p.off_fVp = take(sizeof(double) * (size_t)nb * mmax * mmax);
-  p.off_fgc = take(sizeof(double) * (size_t)nb * mmax);
-  p.off_fgs = take(sizeof(double) * (size_t)nb * mmax);
-  p.off_fv = take(sizeof(double) * (size_t)nb * mmax);
-  p.off_frho = take(sizeof(double) * nb);
-  p.off_fmark = take(sizeof(int) * (size_t)N);
+  // measurement records and scratch, one per interior boundary (or tau = beta)
+  const size_t slots = nb > 1 ? nb - 1 : 1;
+  p.off_mpart = take(sizeof(double) * slots * (obs_count(N, ns) + 1));
+  p.mscr_stride = meas_stride(N, mmax);
+  p.off_mscr = take(sizeof(double) * slots * p.mscr_stride);
+  // Fock-phase scratch, one copy per spin (the two spins run concurrently)
+  p.off_fq = take(sizeof(double) * 2 * (size_t)nb * N);
+  p.off_fw = take(sizeof(double) * 2 * (size_t)N);
+  p.off_fVp = take(sizeof(double) * 2 * (size_t)nb * mmax * mmax);
+  p.off_fgc = take(sizeof(double) * 2 * (size_t)nb * mmax);
+  p.off_fgs = take(sizeof(double) * 2 * (size_t)nb * mmax);
+  p.off_fv = take(sizeof(double) * 2 * (size_t)nb * mmax);
+  p.off_frho = take(sizeof(double) * 2 * nb);
+  p.off_fmark = take(sizeof(int) * 2 * (size_t)N);
   p.off_obs = take(sizeof(double) * obs_count(N, ns));
   p.off_dbg = take(sizeof(double) * (N <= 64 ? std::max(8, 2 * N * N) : 8));
   p.off_col = take(sizeof(int) * (ncol + 1));
@@ -195,6 +226,9 @@ static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int
   p.off_epsf = take(sizeof(double) * N);
   p.off_eps = take(sizeof(double) * N);
   p.off_sub = take(sizeof(int) * N);
+  p.off_bij = take(sizeof(int) * nbonds);
+  p.off_bci = take(nbonds);
+  p.off_coef = take(sizeof(double) * 2 * kMaxCoef);
   p.total = o;
   return p;
 }
@@ -356,6 +390,9 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
     d.T[s] = (double *)(base + p.off_T[s]);
     d.Aw[s] = (double *)(base + p.off_Aw[s]);
   }
+  d.mpart = (double *)(base + p.off_mpart);
+  d.mscr = (double *)(base + p.off_mscr);
+  d.mscr_stride = p.mscr_stride;
   d.fq = (double *)(base + p.off_fq);
   d.fw = (double *)(base + p.off_fw);
   d.fVp = (double *)(base + p.off_fVp);
@@ -396,6 +433,29 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
     }
   }
   hcol[lat->n_colors] = (int)hbi.size();
+  // compact copy: packed site pair and an index into the distinct coefficients
+  std::vector<int> hbij(hbi.size());
+  std::vector<uint8_t> hbci(hbi.size());
+  std::vector<double> hcoef;
+  int ncoef = N <= 65535 ? 0 : -1;
+  for (size_t b = 0; b < hbi.size() && ncoef >= 0; ++b) {
+    hbij[b] = hbi[b] | (hbj[b] << 16);
+    int ci = -1;
+    for (int q = 0; q < ncoef; ++q)
+      if (hcoef[2 * q] == hdiag[b] && hcoef[2 * q + 1] == hoff[b]) { ci = q; break; }
+    if (ci < 0) {
+      if (ncoef == kMaxCoef) { ncoef = -1; break; }
+      hcoef.push_back(hdiag[b]);
+      hcoef.push_back(hoff[b]);
+      ci = ncoef++;
+    }
+    hbci[b] = (uint8_t)ci;
+  }
+  d.ncoef = ncoef > 0 ? ncoef : 0;
+  d.bond_words = d.ncoef > 0 ? 2 * 2 * kMaxCoef + (int)hbi.size() + ((int)hbi.size() + 3) / 4 : 0;
+  d.bij = (const int *)(base + p.off_bij);
+  d.bci = (const uint8_t *)(base + p.off_bci);
+  d.coef = (const double *)(base + p.off_coef);
   std::vector<double> hepsf(N), heps(N);
   std::vector<int> hsub(N);
   for (int i = 0; i < N; ++i) {
@@ -417,6 +477,9 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   if (e == hipSuccess) e = up(epsf, hepsf.data(), sizeof(double) * N);
   if (e == hipSuccess) e = up(eps, heps.data(), sizeof(double) * N);
   if (e == hipSuccess) e = up(sub, hsub.data(), sizeof(int) * N);
+  if (e == hipSuccess && d.ncoef > 0) e = up((void *)d.bij, hbij.data(), sizeof(int) * hbij.size());
+  if (e == hipSuccess && d.ncoef > 0) e = up((void *)d.bci, hbci.data(), hbci.size());
+  if (e == hipSuccess && d.ncoef > 0) e = up((void *)d.coef, hcoef.data(), sizeof(double) * hcoef.size());
   if (e == hipSuccess && fields) {
     std::vector<int8_t> f((size_t)L * N);
     for (size_t t = 0; t < f.size(); ++t) f[t] = fields[t] > 0 ? 1 : -1;
@@ -429,7 +492,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   const int draw_occ = (occ_up ? 0 : 1) | (occ_dn ? 0 : 2);
   if (!fields || draw_occ) e = launch_init(w->d_desc, fields ? 0 : 1, draw_occ, ctx->stream);
   const LaunchCfg cf = launch_cfg(&w, 1);
-  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, cf.mm, cf.phi_left, 1, ctx->stream);
+  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, cf.left, 1, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return cleanup(fail(LECQMC_EDEVICE, "init: %s", hipGetErrorString(e)));
   ctx->used += p.total;
@@ -458,9 +521,10 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
   lecqmc_ctx *c = w->ctx;
   const LaunchCfg cf = launch_cfg(&w, 1);
   for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.mm, cf.phi_left, st); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.mm, cf.phi_fwd, do_measure, st); }));
-    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.mm, cf.phi_fock, st); }));
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.left, st); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.fwd, do_measure, st); }));
+    if (do_measure) HIPCHK(launch_measure(w->d_desc, 1, std::max(1, w->nblk - 1), cf.meas, st));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.fock, st); }));
   }
   return 0;
 }
@@ -484,9 +548,10 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
   HIPCHK(hipMemcpy(c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
   const LaunchCfg cf = launch_cfg(ws, n);
   for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return launch_left_stack(c->d_batch, n, cf.mm, cf.phi_left, c->stream); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(c->d_batch, n, cf.mm, cf.phi_fwd, do_measure, c->stream); }));
-    HIPCHK(timed(c, 2, [&] { return launch_fock(c->d_batch, n, cf.mm, cf.phi_fock, c->stream); }));
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(c->d_batch, n, cf.left, c->stream); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(c->d_batch, n, cf.fwd, do_measure, c->stream); }));
+    if (do_measure) HIPCHK(launch_measure(c->d_batch, n, cf.slots, cf.meas, c->stream));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(c->d_batch, n, cf.fock, c->stream); }));
   }
   return 0;
 }
@@ -495,7 +560,7 @@ extern "C" int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *s
   if (!w || !log_abs_w || !sign) return fail(LECQMC_EINVAL, "null argument");
   HIPCHK(hipSetDevice(w->ctx->device));
   const LaunchCfg cf = launch_cfg(&w, 1);
-  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.mm, cf.phi_left, 0, w->ctx->stream));
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.left, 0, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
   HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
@@ -510,8 +575,8 @@ extern "C" int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
   HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
-  *log_abs_w = sc.logw;
-  *sign = sc.sign;
+  *log_abs_w = sc.logw + sc.fock_logw[0] + sc.fock_logw[1];
+  *sign = sc.sign * sc.fock_sign[0] * sc.fock_sign[1];
   return 0;
 }
 
@@ -541,8 +606,8 @@ extern "C" int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st) {
   HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   st->flip_attempts = sc.flip_att;
   st->flip_accepts = sc.flip_acc;
-  st->swap_attempts = sc.swap_att;
-  st->swap_accepts = sc.swap_acc;
+  st->swap_attempts = sc.swap_att[0] + sc.swap_att[1];
+  st->swap_accepts = sc.swap_acc[0] + sc.swap_acc[1];
   st->max_wrap_err = sc.max_wrap;
   st->logw_drift = sc.logw_drift;
   st->qr_shifted = sc.qr_shifted;
@@ -592,7 +657,7 @@ extern "C" int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const in
   sc.sweep = sweep_counter;
   HIPCHK(hipMemcpy(w->h.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
   const LaunchCfg cf = launch_cfg(&w, 1);
-  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.mm, cf.phi_left, 1, w->ctx->stream));
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.left, 1, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   return check_status(w);
 }

@@ -15,10 +15,13 @@ enum Stream : uint32_t { kFlip = 1, kSwapK = 2, kSwapJ = 3, kSwapAcc = 4, kInitF
 // Scalars of one walker that kernels update (device memory).
 struct Scalars {
   unsigned long long sweep;     // completed sweeps
-  double logw;                  // tracked log|W|
+  double logw;                  // tracked log|W| (up to the pending Fock terms below)
   int sign;                     // tracked sign
   int status;                   // 0 ok, bit 1 = QR shift used, bit 2 = singular inverse
-  long long flip_att, flip_acc, swap_att, swap_acc, qr_shifted;
+  long long flip_att, flip_acc, qr_shifted;
+  long long swap_att[2], swap_acc[2];   // per spin (one Fock workgroup per spin)
+  double fock_logw[2];          // log|r| of accepted swaps per spin, folded in by the next forward pass
+  int fock_sign[2];
   double max_wrap, logw_drift;
   double fresh_logw;            // written by the fresh-weight kernel
   int fresh_sign;
@@ -39,6 +42,12 @@ struct WalkerDesc {
   const int *bi, *bj;           // [nbonds], grouped by colour
   const double *bdiag, *boff;   // cosh(dtau h), -sinh(dtau h)
   const double *bh;             // h
+  // compact copy for LDS: i | j << 16, index of (cosh, -sinh) in coef
+  const int *bij;               // [nbonds]
+  const uint8_t *bci;           // [nbonds]
+  const double *coef;           // [ncoef][2]
+  int ncoef;                    // distinct bond coefficients (0 = no compact copy)
+  int bond_words;               // 4-byte words of the compact copy in LDS
   const double *eps_fac;        // exp(-dtau eps_i)
   const double *eps;            // eps_i
   const int *sub;               // sublattice index
@@ -52,28 +61,40 @@ struct WalkerDesc {
   double *PhiR[2];              // [N][ne]
   double *X[2];                 // [N][ne]  (Phi_L transposed)
   double *T[2];                 // [N][ne]  scratch
-  double *Aw[2];                // [N] wrapped diagonal of A at block ends
-  double *fq;                   // [nblk][N] new columns of an addition
-  double *fw;                   // [N] propagated column
-  double *fVp;                  // [nblk][ne_max^2]
-  double *fgc, *fgs;            // [nblk][ne_max]
-  double *fv;                   // [nblk][ne_max]
-  double *frho;                 // [nblk]
-  int *fmark;                   // [N] occupancy marks / permutation scratch
+  double *Aw[2];                // [nblk][N] diagonal of A from the carried inverse at block ends
+  double *mpart;                // [slots][nobs + 1] per-boundary measurement records
+  double *mscr;                 // [slots][mscr_stride] measurement scratch
+  size_t mscr_stride;
+  // Fock-phase scratch, [2 spins] x ...; fVp spin 0 also serves as QR scratch
+  double *fq;                   // [2][nblk][N] new columns of an addition
+  double *fw;                   // [2][N] propagated column
+  double *fVp;                  // [2][nblk][mmax^2]
+  double *fgc, *fgs;            // [2][nblk][mmax]
+  double *fv;                   // [2][nblk][mmax]
+  double *frho;                 // [2][nblk]
+  int *fmark;                   // [2][N] occupancy marks / permutation scratch
   double *obs;                  // [nobs]
   double *dbg;                  // [N*N] parity-surface output (N <= dbg_n) else [8]
   Scalars *sc;
 };
 
-// kernel launchers (lecqmc_kernels.hip); descs = device array of descriptors.
-// phi_elems > 0 keeps the Slater blocks of each walker resident in LDS.
+// LDS plan of one launch: the largest Ne (mm), Slater blocks kept resident
+// (phi_elems doubles, 0 = streamed), right-row staging buffers (streamed
+// forward pass only) and the compact bond tables (bond_words, 0 = read from
+// device memory).
+struct LdsPlan {
+  int mm, phi_elems, stage_ps, bond_words;
+};
 constexpr size_t kLdsLimit = 163840;
-size_t lds_bytes(int max_ne, int phi_elems);
+constexpr int kMaxCoef = 16;
+size_t lds_bytes(const LdsPlan &p);
+// kernel launchers (lecqmc_kernels.hip); descs = device array of descriptors.
 hipError_t launch_init(const WalkerDesc *d_desc, int draw_fields, int draw_occ, hipStream_t st);
-hipError_t launch_fresh_weight(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, int set_tracked, hipStream_t st);
-hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, hipStream_t st);
-hipError_t launch_forward(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, int do_measure, hipStream_t st);
-hipError_t launch_fock(const WalkerDesc *d_descs, int n, int max_ne, int phi_elems, hipStream_t st);
+hipError_t launch_fresh_weight(const WalkerDesc *d_descs, int n, LdsPlan p, int set_tracked, hipStream_t st);
+hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, LdsPlan p, hipStream_t st);
+hipError_t launch_forward(const WalkerDesc *d_descs, int n, LdsPlan p, int do_measure, hipStream_t st);
+hipError_t launch_fock(const WalkerDesc *d_descs, int n, LdsPlan p, hipStream_t st);
+hipError_t launch_measure(const WalkerDesc *d_descs, int n, int slots, LdsPlan p, hipStream_t st);
 hipError_t launch_green(const WalkerDesc *d_desc, int max_ne, int boundary, int spin, double *G, hipStream_t st);
 hipError_t launch_flip_ratio(const WalkerDesc *d_desc, int max_ne, int slice, int site, hipStream_t st);
 hipError_t launch_swap_ratio(const WalkerDesc *d_desc, int max_ne, int spin, int k, int j, hipStream_t st);

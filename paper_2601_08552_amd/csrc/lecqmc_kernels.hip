@@ -65,23 +65,29 @@ struct Lds {
   double *us;     // [2 buf][S]              staged uniforms
   int8_t *fs;     // [2 buf][S]              staged Ising fields
   double *phi;    // resident Slater blocks, or nullptr
+  double *bonds;  // compact bond tables (coef | bij | bci), or nullptr
   int S;          // sites per staged chunk
+  bool bonds_ok;  // the walker's bond tables were copied into LDS
 };
 
 __host__ __device__ inline int chunk_size(int mm) { return mm <= 16 ? 32 : (mm <= 32 ? 16 : 4); }
 
-size_t lds_bytes(int mm, int phi_elems) {
+__host__ __device__ inline size_t lds_doubles_fixed(int mm, int stage_ps) {
   if (mm < 1) mm = 1;
   const size_t S = chunk_size(mm);
-  const size_t d = 256 + 64 + 4 * (size_t)mm * mm + 8 * 64 + 2 * 64 + 2 * (2 * 2 * S * mm) + 2 * S +
-                   (2 * S + 7) / 8 + (size_t)phi_elems;
+  return 256 + 64 + 4 * (size_t)mm * mm + 8 * 64 + 2 * 64 + (stage_ps ? 2 : 1) * (2 * 2 * S * mm) + 2 * S +
+         (2 * S + 7) / 8;
+}
+
+size_t lds_bytes(const LdsPlan &p) {
+  const size_t d = lds_doubles_fixed(p.mm, p.stage_ps) + (size_t)p.phi_elems + ((size_t)p.bond_words + 1) / 2;
   return d * sizeof(double) + 320 * sizeof(int);
 }
 
 extern __shared__ double lds_raw[];
 
-__device__ Lds carve(int mm, int phi_elems) {
-  if (mm < 1) mm = 1;
+__device__ Lds carve(const LdsPlan &pl) {
+  const int mm = pl.mm < 1 ? 1 : pl.mm;
   const int S = chunk_size(mm);
   Lds L;
   double *p = lds_raw;
@@ -94,13 +100,19 @@ __device__ Lds carve(int mm, int phi_elems) {
   L.vec = p; p += 8 * 64;
   L.uw = p; p += 2 * 64;
   L.xs = p; p += 2 * 2 * S * mm;
-  L.ps = p; p += 2 * 2 * S * mm;
+  L.ps = pl.stage_ps ? p : nullptr; p += pl.stage_ps ? 2 * 2 * S * mm : 0;
   L.us = p; p += 2 * S;
   L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
-  L.phi = phi_elems > 0 ? p : nullptr; p += phi_elems;
+  L.phi = pl.phi_elems > 0 ? p : nullptr; p += pl.phi_elems;
+  L.bonds = pl.bond_words > 0 ? p : nullptr; p += (pl.bond_words + 1) / 2;
   L.iscal = reinterpret_cast<int *>(p);
   L.S = S;
+  L.bonds_ok = false;
   return L;
+}
+__device__ Lds carve(int mm, int phi_elems) {
+  LdsPlan pl{mm, phi_elems, 1, 0};
+  return carve(pl);
 }
 
 #define TID (static_cast<int>(threadIdx.x))
@@ -129,44 +141,137 @@ __device__ double wg_max(double v, double *red) {
 
 // ---------------------------------------------------------------------------
 // Propagation of N x m blocks (rows = sites): checkerboard colour passes and
-// the diagonal Ising/onsite factor.
+// the diagonal Ising/onsite factor.  Each pass is written once for blocks in
+// device memory and once for blocks resident in LDS (address-space-typed
+// pointers, so the bond-table loads are not ordered behind LDS stores).
 // ---------------------------------------------------------------------------
-__device__ void colour_pass(const WalkerDesc &w, double *X, int m, int c, bool inverse) {
-  const int b0 = w.col_start[c], nb = w.col_start[c + 1] - b0;
-  const int tot = nb * m;
-  for (int t = TID; t < tot; t += kThreads) {
-    const int b = b0 + t / m, a = t - (t / m) * m;
-    const int i = w.bi[b], j = w.bj[b];
-    const double d = w.bdiag[b], o = inverse ? -w.boff[b] : w.boff[b];
-    const double xi = X[(size_t)i * m + a], xj = X[(size_t)j * m + a];
-    X[(size_t)i * m + a] = d * xi + o * xj;
-    X[(size_t)j * m + a] = o * xi + d * xj;
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) int8_t lds_i8;
+__device__ __forceinline__ lds_f64 *as_lds(double *p) { return (lds_f64 *)p; }
+__device__ __forceinline__ const lds_f64 *as_lds(const double *p) { return (const lds_f64 *)p; }
+__device__ __forceinline__ lds_i8 *as_lds(int8_t *p) { return (lds_i8 *)p; }
+
+typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// bond (i, j, cosh, -sinh) of bond b: from the compact LDS tables when they
+// were loaded, from device memory otherwise
+struct BondSrc {
+  const lds_f64 *coef;
+  const lds_i32 *bij;
+  const lds_u8 *bci;
+  bool lds;
+};
+__device__ __forceinline__ BondSrc bond_src(const Lds &L, const WalkerDesc &w) {
+  BondSrc b;
+  b.lds = L.bonds_ok;
+  double *base = L.bonds ? L.bonds : L.red;
+  b.coef = as_lds(base);
+  b.bij = (const lds_i32 *)(as_lds(base) + 2 * kMaxCoef);
+  b.bci = (const lds_u8 *)(b.bij + w.nbonds);
+  return b;
+}
+__device__ __forceinline__ void bond_get(const WalkerDesc &w, const BondSrc &bs, int b, int &i, int &j, double &d,
+                                         double &o) {
+  if (bs.lds) {
+    const int ij = bs.bij[b];
+    i = ij & 0xffff;
+    j = (int)((unsigned)ij >> 16);
+    const int ci = bs.bci[b];
+    d = bs.coef[2 * ci];
+    o = bs.coef[2 * ci + 1];
+  } else {
+    i = w.bi[b];
+    j = w.bj[b];
+    d = w.bdiag[b];
+    o = w.boff[b];
+  }
+}
+
+// copy the compact bond tables of walker w into LDS (all threads)
+__device__ void load_bonds(const WalkerDesc &w, Lds &L, int plan_words) {
+  L.bonds_ok = L.bonds != nullptr && w.ncoef > 0 && w.bond_words <= plan_words;
+  if (!L.bonds_ok) return;
+  lds_f64 *coef = as_lds(L.bonds);
+  lds_i32 *bij = (lds_i32 *)(coef + 2 * kMaxCoef);
+  lds_u8 *bci = (lds_u8 *)(bij + w.nbonds);
+  for (int t = TID; t < 2 * w.ncoef; t += kThreads) coef[t] = w.coef[t];
+  for (int t = TID; t < w.nbonds; t += kThreads) {
+    bij[t] = w.bij[t];
+    bci[t] = w.bci[t];
   }
   SYNC();
 }
+
+template <typename P>
+__device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc &bs, P X, int m, int c,
+                                              bool inverse) {
+  const int b0 = w.col_start[c], nb = w.col_start[c + 1] - b0;
+  const int tot = nb * m;
+  // four (bond, column) updates per thread per round: all loads first, then
+  // all stores (the bonds of one colour are disjoint, so nothing aliases)
+  for (int t0 = TID; t0 < tot; t0 += 4 * kThreads) {
+    size_t ii[4], jj[4];
+    double xi[4], xj[4], d[4], o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kThreads;
+      ii[u] = jj[u] = 0;
+      xi[u] = xj[u] = d[u] = o[u] = 0.0;
+      if (t < tot) {
+        const int bb = m == 1 ? t : t / m, a = t - bb * m;
+        int i, j;
+        bond_get(w, bs, b0 + bb, i, j, d[u], o[u]);
+        if (inverse) o[u] = -o[u];
+        ii[u] = (size_t)i * m + a;
+        jj[u] = (size_t)j * m + a;
+        xi[u] = X[ii[u]];
+        xj[u] = X[jj[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (t0 + u * kThreads < tot) {
+        X[ii[u]] = d[u] * xi[u] + o[u] * xj[u];
+        X[jj[u]] = o[u] * xi[u] + d[u] * xj[u];
+      }
+  }
+  SYNC();
+}
+
+template <typename P>
+__device__ __forceinline__ void diag_t(const WalkerDesc &w, P X, int m, int l, int sp, bool inverse) {
+  const int8_t *s = w.s + (size_t)(l - 1) * w.N;
+  for (int i = TID; i < w.N; i += kThreads) {
+    const int ss = sp == 0 ? s[i] : -s[i];
+    double f = (ss > 0 ? w.elam : w.emlam) * w.eps_fac[i];
+    if (inverse) f = 1.0 / f;
+    for (int a = 0; a < m; ++a) X[(size_t)i * m + a] *= f;
+  }
+  SYNC();
+}
+
+__device__ __forceinline__ bool in_lds(const void *p) {
+  return __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)p);
+}
+
+__device__ void colour_pass(const WalkerDesc &w, const Lds &L, double *X, int m, int c, bool inverse) {
+  const BondSrc bs = bond_src(L, w);
+  if (in_lds(X)) colour_pass_t(w, bs, as_lds(X), m, c, inverse);
+  else colour_pass_t(w, bs, X, m, c, inverse);
+}
 // X <- E_K X : colour C-1 acts first
-__device__ void apply_ek(const WalkerDesc &w, double *X, int m) {
-  for (int c = w.ncol - 1; c >= 0; --c) colour_pass(w, X, m, c, false);
+__device__ void apply_ek(const WalkerDesc &w, const Lds &L, double *X, int m) {
+  for (int c = w.ncol - 1; c >= 0; --c) colour_pass(w, L, X, m, c, false);
 }
 // X <- E_K^T X : colour 0 acts first
-__device__ void apply_ekT(const WalkerDesc &w, double *X, int m) {
-  for (int c = 0; c < w.ncol; ++c) colour_pass(w, X, m, c, false);
-}
-// X <- E_K^{-T} X : inverse colours, colour C-1 acts first
-__device__ void apply_ekinvT(const WalkerDesc &w, double *X, int m) {
-  for (int c = w.ncol - 1; c >= 0; --c) colour_pass(w, X, m, c, true);
+__device__ void apply_ekT(const WalkerDesc &w, const Lds &L, double *X, int m) {
+  for (int c = 0; c < w.ncol; ++c) colour_pass(w, L, X, m, c, false);
 }
 // X <- D_l^{+-1} X for spin sp (l = 1..L)
 __device__ void apply_diag(const WalkerDesc &w, double *X, int m, int l, int sp, bool inverse) {
-  const int8_t *s = w.s + (size_t)(l - 1) * w.N;
-  const int tot = w.N * m;
-  for (int t = TID; t < tot; t += kThreads) {
-    const int i = t / m;
-    const int ss = sp == 0 ? s[i] : -s[i];
-    const double f = (ss > 0 ? w.elam : w.emlam) * w.eps_fac[i];
-    X[t] *= inverse ? 1.0 / f : f;
-  }
-  SYNC();
+  if (in_lds(X)) diag_t(w, as_lds(X), m, l, sp, inverse);
+  else diag_t(w, X, m, l, sp, inverse);
 }
 
 __device__ void fill_P(const WalkerDesc &w, int sp, double *X) {
@@ -182,19 +287,40 @@ __device__ void copy_global(double *dst, const double *src, size_t n) {
   SYNC();
 }
 
-// out[p][q] = sum_i X[i][p] Y[i][q] over rows i (optionally only sub[i] == a)
-__device__ void gram(const double *X, int mx, const double *Y, int my, int N, double *out,
-                     double *red, const int *sub = nullptr, int sa = 0) {
+// partial sum_i X[i][pa] Y[i][qb] over rows i = i0, i0 + G, ... (optionally
+// only rows with sub[i] == sa), four independent accumulators so that the
+// loads of consecutive rows overlap
+template <typename PX, typename PY>
+__device__ __forceinline__ double gram_rows(PX X, int mx, int pa, PY Y, int my, int qb, int i0, int N, int G,
+                                            const int *sub, int sa) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = i0;
+  if (!sub) {
+#pragma unroll 2
+    for (; i + 3 * G < N; i += 4 * G) {
+      a0 += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+      a1 += X[(size_t)(i + G) * mx + pa] * Y[(size_t)(i + G) * my + qb];
+      a2 += X[(size_t)(i + 2 * G) * mx + pa] * Y[(size_t)(i + 2 * G) * my + qb];
+      a3 += X[(size_t)(i + 3 * G) * mx + pa] * Y[(size_t)(i + 3 * G) * my + qb];
+    }
+    for (; i < N; i += G) a0 += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+  } else {
+    for (; i < N; i += G)
+      if (sub[i] == sa) a0 += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
+template <typename PX, typename PY>
+__device__ void gram_t(PX X, int mx, PY Y, int my, int N, double *out, double *red, const int *sub, int sa) {
   const int P = mx * my;
-  if (P == 0) { SYNC(); return; }
   if (P <= kThreads) {
     const int G = kThreads / P;
     const int g = TID / P, p = TID - g * P;
     double acc = 0.0;
     if (g < G) {
       const int pa = p / my, qb = p - pa * my;
-      for (int i = g; i < N; i += G)
-        if (!sub || sub[i] == sa) acc += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+      acc = gram_rows(X, mx, pa, Y, my, qb, g, N, G, sub, sa);
     }
     SYNC();
     red[TID] = acc;
@@ -208,13 +334,21 @@ __device__ void gram(const double *X, int mx, const double *Y, int my, int N, do
   } else {
     for (int p = TID; p < P; p += kThreads) {
       const int pa = p / my, qb = p - pa * my;
-      double acc = 0.0;
-      for (int i = 0; i < N; ++i)
-        if (!sub || sub[i] == sa) acc += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
-      out[p] = acc;
+      out[p] = gram_rows(X, mx, pa, Y, my, qb, 0, N, 1, sub, sa);
     }
     SYNC();
   }
+}
+
+// out[p][q] = sum_i X[i][p] Y[i][q] over rows i (optionally only sub[i] == a)
+__device__ void gram(const double *X, int mx, const double *Y, int my, int N, double *out,
+                     double *red, const int *sub = nullptr, int sa = 0) {
+  if (mx * my == 0) { SYNC(); return; }
+  const bool lx = in_lds(X), ly = in_lds(Y);
+  if (lx && ly) gram_t(as_lds(X), mx, as_lds(Y), my, N, out, red, sub, sa);
+  else if (lx) gram_t(as_lds(X), mx, Y, my, N, out, red, sub, sa);
+  else if (ly) gram_t(X, mx, as_lds(Y), my, N, out, red, sub, sa);
+  else gram_t(X, mx, Y, my, N, out, red, sub, sa);
 }
 
 // Cholesky G = R^T R in place (upper triangle of A); false on a non-positive pivot.
@@ -451,12 +585,6 @@ __device__ __forceinline__ double lane_read(double v, int lane) {
 // Register-tiled version for Ne <= 8T: lane (ar, bc) of a half holds rows
 // ar*2T .. ar*2T+2T-1 and columns bc*T .. bc*T+T-1 of its spin's inverse.
 // ---------------------------------------------------------------------------
-typedef __attribute__((address_space(3))) double lds_f64;
-typedef __attribute__((address_space(3))) int8_t lds_i8;
-__device__ __forceinline__ lds_f64 *as_lds(double *p) { return (lds_f64 *)p; }
-__device__ __forceinline__ const lds_f64 *as_lds(const double *p) { return (const lds_f64 *)p; }
-__device__ __forceinline__ lds_i8 *as_lds(int8_t *p) { return (lds_i8 *)p; }
-
 // log|W| bookkeeping of accepted flips: a mantissa product renormalised by
 // exponent bits (exact power-of-two scaling), logged once per block.
 struct ChainAcc {
@@ -735,7 +863,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
       flush_chunk(w, L, l, (nch - 1) * S, (nch - 1) & 1, phi, resident, mm, 0, kThreads);
       SYNC();
     }
-    for (int s2 = 0; s2 < 2; ++s2) apply_ek(w, phi[s2], w.ne[s2]);
+    for (int s2 = 0; s2 < 2; ++s2) apply_ek(w, L, phi[s2], w.ne[s2]);
   }
   if constexpr (T > 0) {
     if (TID < 64) {
@@ -758,8 +886,14 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
 // boundary, accumulated sign-weighted in the observable layout of the ABI.
 // q = 0 sums use traces of Ne x Ne sublattice blocks, O(N Ne^2).
 // ---------------------------------------------------------------------------
-__device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR[2], double *const XL[2],
-                              const double *Ms[2], int sgn, Lds &L) {
+// Scratch per call: T[2] (N x Ne each), Ad[2] (N each), Afull (2 N^2 when N <= 64).
+struct MeasScratch {
+  double *T[2];
+  double *Ad[2];
+  double *Afull;
+};
+__device__ void measure_point(const WalkerDesc &w, double *const PR[2], double *const XL[2], const double *Ms[2],
+                              int sgn, Lds &L, double *obs, const MeasScratch &ms) {
   const int N = w.N, ns = w.nsub;
   const double sg = (double)sgn;
   // T_s = Phi_R M_s^{-1}
@@ -770,7 +904,7 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
       const int i = t / m, b = t - (t / m) * m;
       double s = 0.0;
       for (int a = 0; a < m; ++a) s += PR[sp][(size_t)i * m + a] * Ms[sp][a * m + b];
-      w.T[sp][t] = s;
+      ms.T[sp][t] = s;
     }
   }
   SYNC();
@@ -781,9 +915,9 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
     for (int sp = 0; sp < 2; ++sp) {
       const int m = w.ne[sp];
       double s = 0.0;
-      for (int b = 0; b < m; ++b) s += w.T[sp][(size_t)i * m + b] * XL[sp][(size_t)i * m + b];
+      for (int b = 0; b < m; ++b) s += ms.T[sp][(size_t)i * m + b] * XL[sp][(size_t)i * m + b];
       ad[sp] = s;
-      w.Aw[sp][i] = s;
+      ms.Ad[sp][i] = s;
     }
     docc += ad[0] * ad[1];
     eon += w.eps[i] * (ad[0] + ad[1]);
@@ -797,7 +931,7 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
     for (int sp = 0; sp < 2; ++sp) {
       double v = 0.0;
       for (int i = TID; i < N; i += kThreads)
-        if (w.sub[i] == a) v += w.Aw[sp][i];
+        if (w.sub[i] == a) v += ms.Ad[sp][i];
       v = wg_sum(v, L.red);
       if (TID == 0) L.scal[32 + 2 * a + sp] = v;
     }
@@ -810,14 +944,14 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
     for (int sp = 0; sp < 2; ++sp) {
       const int m = w.ne[sp];
       for (int q = 0; q < m; ++q)
-        s += w.T[sp][(size_t)i * m + q] * XL[sp][(size_t)j * m + q] +
-             w.T[sp][(size_t)j * m + q] * XL[sp][(size_t)i * m + q];
+        s += ms.T[sp][(size_t)i * m + q] * XL[sp][(size_t)j * m + q] +
+             ms.T[sp][(size_t)j * m + q] * XL[sp][(size_t)i * m + q];
     }
     ek += w.bh[b] * s;
   }
   ek = wg_sum(ek, L.red);
   // sublattice traces
-  double *szz = w.obs + 8, *spar = w.obs + 8 + ns * ns;
+  double *szz = obs + 8, *spar = obs + 8 + ns * ns;
   double szz_tot = 0.0, spar_tot = 0.0;
   const int mu = w.ne[0], md = w.ne[1];
   for (int a = 0; a < ns; ++a)
@@ -826,8 +960,8 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
       for (int sp = 0; sp < 2; ++sp) {
         const int m = w.ne[sp];
         // Y_a = sum_{i in a} X_i^T T_i  (m x m), trace(Y_a Y_b)
-        gram(XL[sp], m, w.T[sp], m, N, L.A, L.red, w.sub, a);
-        gram(XL[sp], m, w.T[sp], m, N, L.B, L.red, w.sub, b);
+        gram(XL[sp], m, ms.T[sp], m, N, L.A, L.red, w.sub, a);
+        gram(XL[sp], m, ms.T[sp], m, N, L.B, L.red, w.sub, b);
         double tr = 0.0;
         for (int t = TID; t < m * m; t += kThreads) {
           const int p = t / m, q = t % m;
@@ -842,14 +976,14 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
       const double cross = nua * ndb + nda * nub;
       const double zz = 0.25 * (same[0] + same[1] - cross);
       // Z^a = sum_{i in a} X_up,i^T T_dn,i ; Z'^b = sum_{j in b} T_up,j^T X_dn,j
-      gram(XL[0], mu, w.T[1], md, N, L.A, L.red, w.sub, a);
-      gram(w.T[0], mu, XL[1], md, N, L.B, L.red, w.sub, b);
+      gram(XL[0], mu, ms.T[1], md, N, L.A, L.red, w.sub, a);
+      gram(ms.T[0], mu, XL[1], md, N, L.B, L.red, w.sub, b);
       double d1 = 0.0;
       for (int t = TID; t < mu * md; t += kThreads) d1 += L.A[t] * L.B[t];
       d1 = wg_sum(d1, L.red);
       // Z'^a and Z^b
-      gram(w.T[0], mu, XL[1], md, N, L.A, L.red, w.sub, a);
-      gram(XL[0], mu, w.T[1], md, N, L.B, L.red, w.sub, b);
+      gram(ms.T[0], mu, XL[1], md, N, L.A, L.red, w.sub, a);
+      gram(XL[0], mu, ms.T[1], md, N, L.B, L.red, w.sub, b);
       double d2 = 0.0;
       for (int t = TID; t < mu * md; t += kThreads) d2 += L.A[t] * L.B[t];
       d2 = wg_sum(d2, L.red);
@@ -864,29 +998,29 @@ __device__ __noinline__ void measure_point(const WalkerDesc &w, double *const PR
       spar_tot += xy;
     }
   if (TID == 0) {
-    w.obs[0] += sg;
-    w.obs[1] += 1.0;
-    w.obs[2] += sg * docc / N;
-    w.obs[3] += sg * ek / N;
-    w.obs[4] += sg * spar_tot / w.ncells;
-    w.obs[5] += sg * szz_tot / w.ncells;
-    w.obs[6] += sg * eon / N;
-    w.obs[7] += sg * dens / N;
+    obs[0] += sg;
+    obs[1] += 1.0;
+    obs[2] += sg * docc / N;
+    obs[3] += sg * ek / N;
+    obs[4] += sg * spar_tot / w.ncells;
+    obs[5] += sg * szz_tot / w.ncells;
+    obs[6] += sg * eon / N;
+    obs[7] += sg * dens / N;
   }
   SYNC();
   if (N <= 64) {
     // all-pair correlations from explicit A matrices (small lattices)
-    double *Au = w.dbg, *Ad = w.dbg + N * N;
+    double *Au = ms.Afull, *Ad = ms.Afull + N * N;
     for (int t = TID; t < N * N; t += kThreads) {
       const int i = t / N, j = t % N;
       double su = 0.0, sd = 0.0;
-      for (int q = 0; q < mu; ++q) su += w.T[0][(size_t)i * mu + q] * XL[0][(size_t)j * mu + q];
-      for (int q = 0; q < md; ++q) sd += w.T[1][(size_t)i * md + q] * XL[1][(size_t)j * md + q];
+      for (int q = 0; q < mu; ++q) su += ms.T[0][(size_t)i * mu + q] * XL[0][(size_t)j * mu + q];
+      for (int q = 0; q < md; ++q) sd += ms.T[1][(size_t)i * md + q] * XL[1][(size_t)j * md + q];
       Au[t] = su;
       Ad[t] = sd;
     }
     SYNC();
-    double *ss = w.obs + 8 + 2 * ns * ns, *nn = ss + N * N, *nu = nn + N * N, *nd = nu + N;
+    double *ss = obs + 8 + 2 * ns * ns, *nn = ss + N * N, *nu = nn + N * N, *nd = nu + N;
     for (int t = TID; t < N * N; t += kThreads) {
       const int i = t / N, j = t % N;
       const double d = (i == j) ? 1.0 : 0.0;
@@ -920,7 +1054,7 @@ __device__ double right_stack(const WalkerDesc &w, int sp, Lds &L, double *Phi) 
     const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
     for (int l = l0; l <= l1; ++l) {
       apply_diag(w, Phi, m, l, sp, false);
-      apply_ek(w, Phi, m);
+      apply_ek(w, L, Phi, m);
     }
     double *Q = w.RQ[sp] + (size_t)(k - 1) * N * m;
     double *V = w.RV[sp] + (size_t)(k - 1) * m * m;
@@ -976,10 +1110,10 @@ __global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *descs, int 
 }
 
 // Fresh log-weight from the current (eta, s): right stack + inverse at beta.
-__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *descs, int mm, int phi_elems,
-                                                           int set_tracked) {
+__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *descs, LdsPlan pl, int set_tracked) {
   const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm, phi_elems);
+  Lds L = carve(pl);
+  load_bonds(w, L, pl.bond_words);
   double la = 0.0;
   int sg = 1;
   for (int sp = 0; sp < 2; ++sp) {
@@ -994,7 +1128,12 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *des
   if (TID == 0) {
     w.sc->fresh_logw = la;
     w.sc->fresh_sign = sg;
-    if (set_tracked) { w.sc->logw = la; w.sc->sign = sg; }
+    if (set_tracked) {
+      w.sc->logw = la;
+      w.sc->sign = sg;
+      w.sc->fock_logw[0] = w.sc->fock_logw[1] = 0.0;
+      w.sc->fock_sign[0] = w.sc->fock_sign[1] = 1;
+    }
   }
 }
 
@@ -1002,11 +1141,13 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *des
 // Y <- E_K^T Y, store X'_l = Y (the left state at the flip point of slice l,
 // (Phi_L(l) E_K)^T), Y <- D_l Y; at every block boundary a thin QR, LS[k-1] = Q.
 // LS[n] = P.  Y stays in LDS when it fits.
-__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs, int mm, int phi_elems) {
-  const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm, phi_elems);
+__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs, LdsPlan pl) {
+  const WalkerDesc &w = descs[blockIdx.x >> 1];
+  Lds L = carve(pl);
+  load_bonds(w, L, pl.bond_words);
   const int N = w.N;
-  for (int sp = 0; sp < 2; ++sp) {
+  {
+    const int sp = blockIdx.x & 1;
     const int m = w.ne[sp];
     double *Y = L.phi ? L.phi : w.X[sp];
     fill_P(w, sp, Y);
@@ -1014,12 +1155,12 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs
     for (int k = w.nblk; k >= 1; --k) {
       const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
       for (int l = l1; l >= l0; --l) {
-        apply_ekT(w, Y, m);
+        apply_ekT(w, L, Y, m);
         copy_global(w.LX[sp] + (size_t)(l - 1) * N * m, Y, (size_t)N * m);
         apply_diag(w, Y, m, l, sp, false);
       }
       double *Q = w.LS[sp] + (size_t)(k - 1) * N * m;
-      cholqr(Y, w.T[sp], Q, Y, nullptr, w.fVp, N, m, L, w.sc);
+      cholqr(Y, w.T[sp], Q, Y, nullptr, w.fVp + (size_t)sp * w.nblk * w.mmax * w.mmax, N, m, L, w.sc);
     }
   }
 }
@@ -1027,19 +1168,26 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs
 // Forward pass over all slices with the HS-field flips, stabilisation at
 // block ends (push (Q_k, V_k)), wrap check and measurements at interior
 // boundaries, and the fresh weight and inverse at tau = beta.
-__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, int mm, int phi_elems, int do_measure) {
+template <int TSEL>
+__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, LdsPlan pl, int want_aw) {
   const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm, phi_elems);
+  Lds L = carve(pl);
+  const int mm = pl.mm < 1 ? 1 : pl.mm;
+  load_bonds(w, L, pl.bond_words);
   const int N = w.N, n = w.nblk;
   const bool resident = L.phi != nullptr;
   const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
   double *const phi[2] = {resident ? L.phi : w.PhiR[0], resident ? L.phi + (size_t)N * w.ne[0] : w.PhiR[1]};
-  const int mx = max(w.ne[0], w.ne[1]);
-  const int tsel = mx <= 8 ? 1 : (mx <= 16 ? 2 : (mx <= 32 ? 4 : 0));
+  if (TID == 0) {
+    Scalars *sc = w.sc;
+    sc->logw += sc->fock_logw[0] + sc->fock_logw[1];
+    sc->sign *= sc->fock_sign[0] * sc->fock_sign[1];
+    sc->fock_logw[0] = sc->fock_logw[1] = 0.0;
+    sc->fock_sign[0] = sc->fock_sign[1] = 1;
+  }
   ChainAcc acc{0.0, 1.0, 0, 0};
   for (int sp = 0; sp < 2; ++sp) fill_P(w, sp, phi[sp]);
   double ld_tot = 0.0;
-  double maxwrap = 0.0;
   for (int k = 1; k <= n; ++k) {
     const int l0 = (k - 1) * w.nstab + 1;
     // fresh inverse at the flip point of the block's first slice
@@ -1052,18 +1200,14 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, i
       if (m > 0 && !gj_inverse(L.A, sp ? L.Ms1 : L.Ms0, m, L, &la, &sg))
         if (TID == 0) w.sc->status |= 4;
     }
-    switch (tsel) {
-      case 1: forward_block<1>(w, k, sweep, L, phi, resident, mm, acc); break;
-      case 2: forward_block<2>(w, k, sweep, L, phi, resident, mm, acc); break;
-      case 4: forward_block<4>(w, k, sweep, L, phi, resident, mm, acc); break;
-      default: forward_block<0>(w, k, sweep, L, phi, resident, mm, acc); break;
-    }
-    // block end: diagonal of A with the updated inverse, kept for the wrap check
-    if (k < n)
+    forward_block<TSEL>(w, k, sweep, L, phi, resident, mm, acc);
+    // block end: diagonal of A from the updated inverse, kept for the wrap check
+    if (k < n && want_aw)
       for (int sp = 0; sp < 2; ++sp) {
         const int m = w.ne[sp];
         const double *Ms = sp ? L.Ms1 : L.Ms0;
         const double *Xb = w.LS[sp] + (size_t)k * N * m;
+        double *aw = w.Aw[sp] + (size_t)(k - 1) * N;
         for (int i = TID; i < N; i += kThreads) {
           double s = 0.0;
           for (int p = 0; p < m; ++p) {
@@ -1071,7 +1215,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, i
             for (int q = 0; q < m; ++q) t += Ms[p * m + q] * Xb[(size_t)i * m + q];
             s += phi[sp][(size_t)i * m + p] * t;
           }
-          w.Aw[sp][i] = s;
+          aw[i] = s;
         }
         SYNC();
       }
@@ -1080,40 +1224,6 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, i
       double *Q = w.RQ[sp] + (size_t)(k - 1) * N * m;
       double *V = w.RV[sp] + (size_t)(k - 1) * m * m;
       ld_tot += cholqr(phi[sp], w.T[sp], Q, phi[sp], V, w.fVp, N, m, L, w.sc);
-    }
-    if (k < n) {
-      // fresh boundary quantities: Phi_R = Q_k, Phi_L = LS[k]^T
-      int fresh_sign = 1;
-      for (int sp = 0; sp < 2; ++sp) {
-        const int m = w.ne[sp];
-        double *Ms = sp ? L.Ms1 : L.Ms0;
-        const double *Xb = w.LS[sp] + (size_t)k * N * m;
-        gram(Xb, m, phi[sp], m, N, L.A, L.red);
-        double la;
-        int sg = 1;
-        if (m > 0) {
-          if (!gj_inverse(L.A, Ms, m, L, &la, &sg))
-            if (TID == 0) w.sc->status |= 4;
-          double dmax = 0.0;
-          for (int i = TID; i < N; i += kThreads) {
-            double s = 0.0;
-            for (int p = 0; p < m; ++p) {
-              double t = 0.0;
-              for (int q = 0; q < m; ++q) t += Ms[p * m + q] * Xb[(size_t)i * m + q];
-              s += phi[sp][(size_t)i * m + p] * t;
-            }
-            dmax = fmax(dmax, fabs(s - w.Aw[sp][i]));
-          }
-          dmax = wg_max(dmax, L.red);
-          maxwrap = fmax(maxwrap, dmax);
-        }
-        fresh_sign *= sg;
-      }
-      if (do_measure) {
-        double *const XL[2] = {w.LS[0] + (size_t)k * N * w.ne[0], w.LS[1] + (size_t)k * N * w.ne[1]};
-        const double *Ms[2] = {L.Ms0, L.Ms1};
-        measure_point(w, phi, XL, Ms, fresh_sign, L);
-      }
     }
   }
   // tau = beta: inverse of P^T Q_n and the fresh weight
@@ -1125,30 +1235,108 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, i
     ld_tot += la;
     sg_tot *= sg;
   }
-  if (n == 1 && do_measure) {
-    for (int sp = 0; sp < 2; ++sp) {
-      const int m = w.ne[sp];
-      fill_P(w, sp, w.X[sp]);
-      double *dst = sp ? L.Ms1 : L.Ms0;
-      for (int t = TID; t < m * m; t += kThreads) dst[t] = w.Minv[sp][t];
-      SYNC();
-    }
-    double *const XL[2] = {w.X[0], w.X[1]};
-    const double *Ms[2] = {L.Ms0, L.Ms1};
-    measure_point(w, phi, XL, Ms, sg_tot, L);
-  }
   if (TID == 0) {
     Scalars *sc = w.sc;
     const double tracked = sc->logw + acc_total(acc);
     const double drift = fabs(tracked - ld_tot);
     if (drift > sc->logw_drift) sc->logw_drift = drift;
-    if (maxwrap > sc->max_wrap) sc->max_wrap = maxwrap;
     sc->logw = ld_tot;
     sc->sign = sg_tot;
     sc->fresh_logw = ld_tot;
     sc->fresh_sign = sg_tot;
     if (!(w.flags & 2)) sc->flip_att += (long long)w.N * w.L;
     sc->flip_acc += acc.nacc;
+    sc->sweep = sweep;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Measurements after the forward pass.  The fresh Green's function at the
+// interior boundary k is fixed by the stored pair (LS[k], Q_k): LS[k] was
+// built from the fields of the blocks above k before they were swept, Q_k
+// from the swept fields of the blocks up to k, which is the configuration
+// the sweep passes through at that boundary.  One workgroup per (walker,
+// boundary) writes a partial record (estimators, wrap error); k_measure_sum
+// adds the records of a walker in boundary order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int meas_slots(const WalkerDesc &w) { return w.nblk > 1 ? w.nblk - 1 : 1; }
+
+__global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *descs, LdsPlan pl, int slots) {
+  const WalkerDesc &w = descs[blockIdx.x / slots];
+  const int q = blockIdx.x % slots;
+  if (q >= meas_slots(w)) return;
+  Lds L = carve(pl);
+  const int N = w.N;
+  const size_t rec = (size_t)w.nobs + 1;
+  double *part = w.mpart + (size_t)q * rec;
+  double *scr = w.mscr + (size_t)q * w.mscr_stride;
+  MeasScratch ms;
+  ms.T[0] = scr;
+  ms.T[1] = scr + (size_t)N * w.mmax;
+  ms.Ad[0] = scr + (size_t)2 * N * w.mmax;
+  ms.Ad[1] = ms.Ad[0] + N;
+  ms.Afull = ms.Ad[1] + N;
+  for (int t = TID; t < (int)rec; t += kThreads) part[t] = 0.0;
+  double *PR[2], *XL[2];
+  const bool at_beta = w.nblk == 1;
+  const int k = q + 1;
+  int sg = 1;
+  double wrap = 0.0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    double *Ms = sp ? L.Ms1 : L.Ms0;
+    if (at_beta) {
+      PR[sp] = w.RQ[sp];
+      XL[sp] = w.X[sp];
+      fill_P(w, sp, XL[sp]);
+      for (int t = TID; t < m * m; t += kThreads) Ms[t] = w.Minv[sp][t];
+      SYNC();
+      continue;
+    }
+    PR[sp] = w.RQ[sp] + (size_t)(k - 1) * N * m;
+    XL[sp] = w.LS[sp] + (size_t)k * N * m;
+    gram(XL[sp], m, PR[sp], m, N, L.A, L.red);
+    double la;
+    int s2 = 1;
+    if (m > 0) {
+      if (!gj_inverse(L.A, Ms, m, L, &la, &s2))
+        if (TID == 0) w.sc->status |= 4;
+      // wrap check: diagonal of A from the inverse carried through the block
+      const double *aw = w.Aw[sp] + (size_t)(k - 1) * N;
+      double dmax = 0.0;
+      for (int i = TID; i < N; i += kThreads) {
+        double s = 0.0;
+        for (int p = 0; p < m; ++p) {
+          double t = 0.0;
+          for (int qq = 0; qq < m; ++qq) t += Ms[p * m + qq] * XL[sp][(size_t)i * m + qq];
+          s += PR[sp][(size_t)i * m + p] * t;
+        }
+        dmax = fmax(dmax, fabs(s - aw[i]));
+      }
+      dmax = wg_max(dmax, L.red);
+      wrap = fmax(wrap, dmax);
+    }
+    sg *= s2;
+  }
+  if (at_beta) sg = w.sc->sign;  // sign of prod det(P^T Q_n) set by this sweep's forward pass
+  const double *Msp[2] = {L.Ms0, L.Ms1};
+  measure_point(w, PR, XL, Msp, sg, L, part, ms);
+  if (TID == 0) part[w.nobs] = wrap;
+}
+
+__global__ void __launch_bounds__(kThreads) k_measure_sum(const WalkerDesc *descs) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  const int slots = meas_slots(w);
+  const size_t rec = (size_t)w.nobs + 1;
+  for (int t = TID; t < w.nobs; t += kThreads) {
+    double s = w.obs[t];
+    for (int q = 0; q < slots; ++q) s += w.mpart[(size_t)q * rec + t];
+    w.obs[t] = s;
+  }
+  if (TID == 0) {
+    double mx = w.sc->max_wrap;
+    for (int q = 0; q < slots; ++q) mx = fmax(mx, w.mpart[(size_t)q * rec + w.nobs]);
+    w.sc->max_wrap = mx;
   }
 }
 
@@ -1170,6 +1358,13 @@ __device__ __forceinline__ int perm_col(int c, int k, int ne) {
 __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc, bool commit,
                           Lds &L, double *fw, double *ratio_out) {
   const int N = w.N, ne = w.ne[sp], m = ne - 1, n = w.nblk, mm = w.mmax;
+  // per-spin Fock scratch
+  double *const fq = w.fq + (size_t)sp * n * N;
+  double *const fVp = w.fVp + (size_t)sp * n * mm * mm;
+  double *const fgc = w.fgc + (size_t)sp * n * mm;
+  double *const fgs = w.fgs + (size_t)sp * n * mm;
+  double *const fv = w.fv + (size_t)sp * n * mm;
+  double *const frho = w.frho + (size_t)sp * n;
   double *H = L.Ms0, *Mp = L.Ms1, *Mred = L.A;
   double *y = L.vec, *z = L.vec + 64, *vsum = L.vec + 128, *acol = L.vec + 192, *brow = L.vec + 256,
          *tv = L.vec + 320;
@@ -1188,7 +1383,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     } else {
       for (int t = TID; t < ne * ne; t += kThreads) H[t] = V[t];
       SYNC();
-      const double *gc = w.fgc + (size_t)(lvl - 1) * mm, *gs = w.fgs + (size_t)(lvl - 1) * mm;
+      const double *gc = fgc + (size_t)(lvl - 1) * mm, *gs = fgs + (size_t)(lvl - 1) * mm;
       for (int r = k; r <= ne - 2; ++r) {
         const double cc = gc[r], ss = gs[r];
         for (int row = TID; row < ne; row += kThreads) {
@@ -1199,7 +1394,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         SYNC();
       }
     }
-    double *gc = w.fgc + (size_t)lvl * mm, *gs = w.fgs + (size_t)lvl * mm;
+    double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
     for (int r = k; r <= ne - 2; ++r) {
       if (TID == 0) {
         const double a = H[r * ne + r], b = H[(r + 1) * ne + r];
@@ -1222,7 +1417,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       if (TID == 0) H[(r + 1) * ne + r] = 0.0;
     }
     SYNC();
-    double *Vp = w.fVp + (size_t)lvl * mm * mm;
+    double *Vp = fVp + (size_t)lvl * mm * mm;
     for (int t = TID; t < ne * ne; t += kThreads) Vp[t] = H[t];
     if (TID == 0) {
       const double last = H[(ne - 1) * ne + (ne - 1)];
@@ -1237,7 +1432,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     double *Tm = L.B;
     for (int t = TID; t < ne * ne; t += kThreads) Tm[t] = w.Minv[sp][t];
     SYNC();
-    const double *gc = w.fgc + (size_t)(n - 1) * mm, *gs = w.fgs + (size_t)(n - 1) * mm;
+    const double *gc = fgc + (size_t)(n - 1) * mm, *gs = fgs + (size_t)(n - 1) * mm;
     for (int r = k; r <= ne - 2; ++r) {
       const double cc = gc[r], ss = gs[r];
       for (int col = TID; col < ne; col += kThreads) {
@@ -1270,10 +1465,10 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       const int l0 = lvl * w.nstab + 1, l1 = min((lvl + 1) * w.nstab, w.L);
       for (int l = l0; l <= l1; ++l) {
         apply_diag(w, fw, 1, l, sp, false);
-        apply_ek(w, fw, 1);
+        apply_ek(w, L, fw, 1);
       }
       const double *Q = w.RQ[sp] + (size_t)lvl * N * ne;
-      const double *gc = w.fgc + (size_t)lvl * mm, *gs = w.fgs + (size_t)lvl * mm;
+      const double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
       for (int a = TID; a < 64; a += kThreads) vsum[a] = 0.0;
       SYNC();
       for (int pass = 0; pass < 2 && m > 0; ++pass) {
@@ -1308,15 +1503,15 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         SYNC();
         break;
       }
-      double *q = w.fq + (size_t)lvl * N;
+      double *q = fq + (size_t)lvl * N;
       for (int i = TID; i < N; i += kThreads) {
         const double v = fw[i] / nrm;
         q[i] = v;
         fw[i] = v;
       }
       if (TID == 0) {
-        for (int a = 0; a < m; ++a) w.fv[(size_t)lvl * mm + a] = vsum[a];
-        w.frho[lvl] = nrm;
+        for (int a = 0; a < m; ++a) fv[(size_t)lvl * mm + a] = vsum[a];
+        frho[lvl] = nrm;
         L.scal[23] += log(nrm);
       }
       SYNC();
@@ -1326,10 +1521,10 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
   double ratio = 0.0;
   if (L.scal[22] == 0.0) {
     const double *Qn = w.RQ[sp] + (size_t)(n - 1) * N * ne;
-    const double *qn = w.fq + (size_t)(n - 1) * N;
+    const double *qn = fq + (size_t)(n - 1) * N;
     const int *occ = w.occ[sp];
     if (TID == 0) {
-      const double *gc = w.fgc + (size_t)(n - 1) * mm, *gs = w.fgs + (size_t)(n - 1) * mm;
+      const double *gc = fgc + (size_t)(n - 1) * mm, *gs = fgs + (size_t)(n - 1) * mm;
       for (int a = 0; a < ne; ++a) tv[a] = Qn[(size_t)j * ne + a];
       for (int r = k; r <= ne - 2; ++r) {
         const double a = tv[r], b = tv[r + 1];
@@ -1364,8 +1559,8 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       if (accepted && commit) {
         for (int lvl = 0; lvl < n; ++lvl) {
           double *Q = w.RQ[sp] + (size_t)lvl * N * ne;
-          const double *gc = w.fgc + (size_t)lvl * mm, *gs = w.fgs + (size_t)lvl * mm;
-          const double *q = w.fq + (size_t)lvl * N;
+          const double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
+          const double *q = fq + (size_t)lvl * N;
           for (int i = TID; i < N; i += kThreads) {
             double *row = Q + (size_t)i * ne;
             for (int r = k; r <= ne - 2; ++r) {
@@ -1376,13 +1571,13 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
             row[ne - 1] = q[i];
           }
           double *V = w.RV[sp] + (size_t)lvl * ne * ne;
-          const double *Vp = w.fVp + (size_t)lvl * mm * mm;
+          const double *Vp = fVp + (size_t)lvl * mm * mm;
           for (int t = TID; t < ne * ne; t += kThreads) {
             const int a = t / ne, b = t % ne;
             double val = 0.0;
             if (a < m && b < m) val = Vp[a * ne + b];
-            else if (b == ne - 1 && a < m) val = w.fv[(size_t)lvl * mm + a];
-            else if (a == ne - 1 && b == ne - 1) val = w.frho[lvl];
+            else if (b == ne - 1 && a < m) val = fv[(size_t)lvl * mm + a];
+            else if (a == ne - 1 && b == ne - 1) val = frho[lvl];
             V[t] = val;
           }
         }
@@ -1403,8 +1598,8 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         for (int a = TID; a < m; a += kThreads) w.occ[sp][a] = nocc[a];
         if (TID == 0) {
           w.occ[sp][ne - 1] = j;
-          w.sc->logw += lr;
-          w.sc->sign *= (int)sr;
+          w.sc->fock_logw[sp] += lr;
+          w.sc->fock_sign[sp] *= (int)sr;
         }
       }
     }
@@ -1417,13 +1612,14 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
 // index of the nth empty site (ascending) of spin sp
 __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
   const int N = w.N, ne = w.ne[sp];
-  for (int i = TID; i < N; i += kThreads) w.fmark[i] = 0;
+  int *const fmark = w.fmark + (size_t)sp * N;
+  for (int i = TID; i < N; i += kThreads) fmark[i] = 0;
   SYNC();
-  for (int a = TID; a < ne; a += kThreads) w.fmark[w.occ[sp][a]] = 1;
+  for (int a = TID; a < ne; a += kThreads) fmark[w.occ[sp][a]] = 1;
   SYNC();
   const int chunk = (N + kThreads - 1) / kThreads;
   int cnt = 0;
-  for (int i = TID * chunk; i < min(N, (TID + 1) * chunk); ++i) cnt += w.fmark[i] == 0;
+  for (int i = TID * chunk; i < min(N, (TID + 1) * chunk); ++i) cnt += fmark[i] == 0;
   int *counts = L.iscal + 64;
   counts[TID] = cnt;
   SYNC();
@@ -1435,7 +1631,7 @@ __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
     }
     int site = -1, c = acc;
     for (int i = owner * chunk; i < min(N, (owner + 1) * chunk); ++i)
-      if (w.fmark[i] == 0) {
+      if (fmark[i] == 0) {
         if (c == nth) { site = i; break; }
         ++c;
       }
@@ -1447,30 +1643,29 @@ __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
   return s;
 }
 
-__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, int mm, int phi_elems) {
-  const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(mm, phi_elems);
-  double *fw = (L.phi && phi_elems >= w.N) ? L.phi : w.fw;
-  const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
-  if (!(w.flags & 1)) {
-    for (int sp = 0; sp < 2; ++sp) {
-      const int ne = w.ne[sp];
-      if (ne == 0 || ne == w.N) continue;
-      for (int t = 0; t < ne; ++t) {
-        const int k = pick(uniform01(w.seed, w.wid, kSwapK, sweep, (uint32_t)sp, (uint32_t)t), ne);
-        const int jn = pick(uniform01(w.seed, w.wid, kSwapJ, sweep, (uint32_t)sp, (uint32_t)t), w.N - ne);
-        const int j = nth_empty(w, sp, jn, L);
-        const double xacc = uniform01(w.seed, w.wid, kSwapAcc, sweep, (uint32_t)sp, (uint32_t)t);
-        const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, fw, nullptr);
-        if (TID == 0) {
-          w.sc->swap_att += 1;
-          if (acc) w.sc->swap_acc += 1;
-        }
-        SYNC();
-      }
+// One workgroup per (walker, spin): the two species have separate stacks,
+// inverses and occupations, so their swap sequences are independent.
+__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, LdsPlan pl) {
+  const WalkerDesc &w = descs[blockIdx.x >> 1];
+  const int sp = blockIdx.x & 1;
+  Lds L = carve(pl);
+  load_bonds(w, L, pl.bond_words);
+  double *fw = (L.phi && pl.phi_elems >= w.N) ? L.phi : w.fw + (size_t)sp * w.N;
+  const uint32_t sweep = (uint32_t)w.sc->sweep;
+  const int ne = w.ne[sp];
+  if ((w.flags & 1) || ne == 0 || ne == w.N) return;
+  for (int t = 0; t < ne; ++t) {
+    const int k = pick(uniform01(w.seed, w.wid, kSwapK, sweep, (uint32_t)sp, (uint32_t)t), ne);
+    const int jn = pick(uniform01(w.seed, w.wid, kSwapJ, sweep, (uint32_t)sp, (uint32_t)t), w.N - ne);
+    const int j = nth_empty(w, sp, jn, L);
+    const double xacc = uniform01(w.seed, w.wid, kSwapAcc, sweep, (uint32_t)sp, (uint32_t)t);
+    const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, fw, nullptr);
+    if (TID == 0) {
+      w.sc->swap_att[sp] += 1;
+      if (acc) w.sc->swap_acc[sp] += 1;
     }
+    SYNC();
   }
-  if (TID == 0) w.sc->sweep += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1483,7 +1678,7 @@ __device__ void right_state(const WalkerDesc &w, int sp, int b, Lds &L) {
   fill_P(w, sp, Phi);
   for (int l = 1; l <= b; ++l) {
     apply_diag(w, Phi, m, l, sp, false);
-    apply_ek(w, Phi, m);
+    apply_ek(w, L, Phi, m);
     if (l % w.nstab == 0 || l == b) cholqr(Phi, w.T[sp], Phi, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
   }
 }
@@ -1494,7 +1689,7 @@ __device__ void left_state(const WalkerDesc &w, int sp, int b, Lds &L) {
   fill_P(w, sp, Y);
   int cnt = 0;
   for (int l = w.L; l > b; --l) {
-    apply_ekT(w, Y, m);
+    apply_ekT(w, L, Y, m);
     apply_diag(w, Y, m, l, sp, false);
     if (++cnt % w.nstab == 0 || l == b + 1) cholqr(Y, w.T[sp], Y, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
   }
@@ -1537,7 +1732,7 @@ __global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *descs
     right_state(w, sp, l - 1, L);
     apply_diag(w, w.PhiR[sp], m, l, sp, false);
     left_state(w, sp, l, L);
-    apply_ekT(w, w.X[sp], m);
+    apply_ekT(w, L, w.X[sp], m);
     gram(w.X[sp], m, w.PhiR[sp], m, N, L.A, L.red);
     double la;
     int sg;
@@ -1583,51 +1778,73 @@ hipError_t launch_init(const WalkerDesc *d, int draw_fields, int draw_occ, hipSt
   hipLaunchKernelGGL(k_init, dim3(1), dim3(kThreads), 0, st, d, draw_fields, draw_occ);
   return hipGetLastError();
 }
-hipError_t launch_fresh_weight(const WalkerDesc *d, int n, int mm, int phi_elems, int set_tracked, hipStream_t st) {
-  mm = clamp_mm(mm);
-  const size_t b = lds_bytes(mm, phi_elems);
+static LdsPlan clamp_plan(LdsPlan p) {
+  p.mm = clamp_mm(p.mm);
+  return p;
+}
+hipError_t launch_fresh_weight(const WalkerDesc *d, int n, LdsPlan p, int set_tracked, hipStream_t st) {
+  p = clamp_plan(p);
+  const size_t b = lds_bytes(p);
   lds_attr(k_fresh_weight, b);
-  hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems, set_tracked);
+  hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), b, st, d, p, set_tracked);
   return hipGetLastError();
 }
-hipError_t launch_left_stack(const WalkerDesc *d, int n, int mm, int phi_elems, hipStream_t st) {
-  mm = clamp_mm(mm);
-  const size_t b = lds_bytes(mm, phi_elems);
+hipError_t launch_left_stack(const WalkerDesc *d, int n, LdsPlan p, hipStream_t st) {
+  p = clamp_plan(p);
+  const size_t b = lds_bytes(p);
   lds_attr(k_left_stack, b);
-  hipLaunchKernelGGL(k_left_stack, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems);
+  hipLaunchKernelGGL(k_left_stack, dim3(2 * n), dim3(kThreads), b, st, d, p);
   return hipGetLastError();
 }
-hipError_t launch_forward(const WalkerDesc *d, int n, int mm, int phi_elems, int do_measure, hipStream_t st) {
-  mm = clamp_mm(mm);
-  const size_t b = lds_bytes(mm, phi_elems);
-  lds_attr(k_forward, b);
-  hipLaunchKernelGGL(k_forward, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems, do_measure);
+// register tile of the flip chain chosen by the largest Ne of the launch
+template <int TSEL>
+static hipError_t launch_forward_t(const WalkerDesc *d, int n, LdsPlan p, int want_aw, hipStream_t st) {
+  const size_t b = lds_bytes(p);
+  lds_attr(k_forward<TSEL>, b);
+  hipLaunchKernelGGL(k_forward<TSEL>, dim3(n), dim3(kThreads), b, st, d, p, want_aw);
   return hipGetLastError();
 }
-hipError_t launch_fock(const WalkerDesc *d, int n, int mm, int phi_elems, hipStream_t st) {
-  mm = clamp_mm(mm);
-  const size_t b = lds_bytes(mm, phi_elems);
+hipError_t launch_measure(const WalkerDesc *d, int n, int slots, LdsPlan p, hipStream_t st) {
+  p = clamp_plan(p);
+  const size_t b = lds_bytes(p);
+  lds_attr(k_measure, b);
+  hipLaunchKernelGGL(k_measure, dim3(n * slots), dim3(kThreads), b, st, d, p, slots);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_measure_sum, dim3(n), dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
+hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int do_measure, hipStream_t st) {
+  p = clamp_plan(p);
+  if (p.mm <= 8) return launch_forward_t<1>(d, n, p, do_measure, st);
+  if (p.mm <= 16) return launch_forward_t<2>(d, n, p, do_measure, st);
+  if (p.mm <= 32) return launch_forward_t<4>(d, n, p, do_measure, st);
+  return launch_forward_t<0>(d, n, p, do_measure, st);
+}
+hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, hipStream_t st) {
+  p = clamp_plan(p);
+  const size_t b = lds_bytes(p);
   lds_attr(k_fock, b);
-  hipLaunchKernelGGL(k_fock, dim3(n), dim3(kThreads), b, st, d, mm, phi_elems);
+  hipLaunchKernelGGL(k_fock, dim3(2 * n), dim3(kThreads), b, st, d, p);
   return hipGetLastError();
 }
 hipError_t launch_green(const WalkerDesc *d, int mm, int b, int sp, double *G, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(mm, 0);
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0});
   lds_attr(k_green, by);
   hipLaunchKernelGGL(k_green, dim3(1), dim3(kThreads), by, st, d, mm, b, sp, G);
   return hipGetLastError();
 }
 hipError_t launch_flip_ratio(const WalkerDesc *d, int mm, int slice, int site, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(mm, 0);
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0});
   lds_attr(k_flip_ratio, by);
   hipLaunchKernelGGL(k_flip_ratio, dim3(1), dim3(kThreads), by, st, d, mm, slice, site);
   return hipGetLastError();
 }
 hipError_t launch_swap_ratio(const WalkerDesc *d, int mm, int sp, int k, int j, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(mm, 0);
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0});
   lds_attr(k_swap_ratio, by);
   hipLaunchKernelGGL(k_swap_ratio, dim3(1), dim3(kThreads), by, st, d, mm, sp, k, j);
   return hipGetLastError();
