@@ -63,6 +63,7 @@ struct Lds {
   double *xs;     // [2 buf][2 spin][S][mm]  staged left rows
   double *ps;     // [2 buf][2 spin][S][mm]  staged right rows (streamed mode)
   double *us;     // [2 buf][S]              staged uniforms
+  double *dl;     // [2 buf][2 spin][S]      staged flip factors Delta
   int8_t *fs;     // [2 buf][S]              staged Ising fields
   double *phi;    // resident Slater blocks, or nullptr
   double *bonds;  // compact bond tables (coef | bij | bci), or nullptr
@@ -75,7 +76,7 @@ __host__ __device__ inline int chunk_size(int mm) { return mm <= 16 ? 32 : (mm <
 __host__ __device__ inline size_t lds_doubles_fixed(int mm, int stage_ps) {
   if (mm < 1) mm = 1;
   const size_t S = chunk_size(mm);
-  return 256 + 64 + 4 * (size_t)mm * mm + 8 * 64 + 2 * 64 + (stage_ps ? 2 : 1) * (2 * 2 * S * mm) + 2 * S +
+  return 256 + 64 + 4 * (size_t)mm * mm + 8 * 64 + 2 * 64 + (stage_ps ? 2 : 1) * (2 * 2 * S * mm) + 2 * S + 4 * S +
          (2 * S + 7) / 8;
 }
 
@@ -102,6 +103,7 @@ __device__ Lds carve(const LdsPlan &pl) {
   L.xs = p; p += 2 * 2 * S * mm;
   L.ps = pl.stage_ps ? p : nullptr; p += pl.stage_ps ? 2 * 2 * S * mm : 0;
   L.us = p; p += 2 * S;
+  L.dl = p; p += 4 * S;
   L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
   L.phi = pl.phi_elems > 0 ? p : nullptr; p += pl.phi_elems;
   L.bonds = pl.bond_words > 0 ? p : nullptr; p += (pl.bond_words + 1) / 2;
@@ -534,10 +536,11 @@ __device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logab
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi2, lo2);
+  // every lane reads a valid source lane for the patterns used here, so the
+  // old value is never kept and no copy of it is made
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double swz16_d(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
@@ -593,123 +596,124 @@ struct ChainAcc {
   int expo;
   long long nacc;
 };
+// prod stays in [1/2, 1): the exponent of every product is moved into expo
 __device__ __forceinline__ void acc_ratio(ChainAcc &acc, double r) {
-  if (r > 1e-300 && r < 1e300) {
-    const double pr = acc.prod * r;
-    int hi = __double2hiint(pr);
-    const int lo = __double2loint(pr);
-    acc.expo += ((hi >> 20) & 0x7ff) - 1022;
-    hi = (hi & 0x800fffff) | (1022 << 20);
-    acc.prod = __hiloint2double(hi, lo);
-  } else {
-    acc.logw += log(r);
-  }
-  acc.nacc += 1;
+  const double pr = acc.prod * r;
+  acc.expo += __builtin_amdgcn_frexp_exp(pr);
+  acc.prod = __builtin_amdgcn_frexp_mant(pr);
 }
 __device__ __forceinline__ double acc_total(const ChainAcc &acc) {
   return acc.logw + log(acc.prod) + (double)acc.expo * 0.69314718055994530942;
 }
+// c = d / r from the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (quadratic convergence to a few ulp of 1/r)
+__device__ __forceinline__ double div_nr(double d, double r) {
+  double y = __builtin_amdgcn_rcp(r);
+  double e = fma(-r, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-r, y, 1.0);
+  y = fma(y, e, y);
+  return d * y;
+}
 
+// Accepted flips of a chunk are returned as a bit mask (bit r = row r of the
+// chunk); the field flip and the row scaling Phi_R[i,:] *= 1 + Delta are
+// applied by flush_chunk, since no later site of the slice reads them.
 template <int T>
-__device__ void chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], const double *xsb_g, int mm,
-                                double *prow_g, int ldp, const double *usb_g, int8_t *fsb_g, int cnt, int S,
-                                ChainAcc &acc) {
+__device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], const double *xsb_g, int mm,
+                                    const double *prow_g, int ldp, const double *usb_g, const double *dsb_g, int cnt,
+                                    int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
   const int m = w.ne[sp];
-  const lds_f64 *xsp = as_lds(xsb_g) + sp * S * mm;
-  lds_f64 *prow = as_lds(prow_g);
+  const lds_f64 *xsp = as_lds(xsb_g) + sp * S * mm + bc * T;
   const lds_f64 *usb = as_lds(usb_g);
-  lds_i8 *fsb = as_lds(fsb_g);
-  const double dpos = w.delta_dn_s, dneg = w.delta_up_s;
-  double x[T], p[2 * T], xn[T], pn[2 * T];
-  int sv = 0, svn = 0;
-  double uv = 0.0, uvn = 0.0;
-  // staged left rows are zero-padded to mm columns; right-row reads are
-  // clamped to a valid column and masked, so every load is unconditional
-  int pcol[2 * T];
-  bool pon[2 * T];
+  const lds_f64 *dsb = as_lds(dsb_g) + sp * S;
+  // right-row columns outside 0..m-1 are read from column 0: the matching
+  // rows and columns of the register inverse are zero, so they add nothing
+  const lds_f64 *prow[2 * T];
 #pragma unroll
   for (int i = 0; i < 2 * T; ++i) {
     const int a = ar * 2 * T + i;
-    pcol[i] = a < m ? a : 0;
-    pon[i] = a < m;
+    prow[i] = as_lds(prow_g) + (a < m ? a : 0);
   }
-  auto load = [&](int r, double (&xx)[T], double (&pp)[2 * T], int &s_, double &u_) {
-#pragma unroll
-    for (int j = 0; j < T; ++j) xx[j] = xsp[r * mm + bc * T + j];
-#pragma unroll
-    for (int i = 0; i < 2 * T; ++i) {
-      const double v = prow[r * ldp + pcol[i]];
-      pp[i] = pon[i] ? v : 0.0;
-    }
-    s_ = fsb[r];
-    u_ = usb[r];
+  struct Row {
+    double x[T], p[2 * T], u, d;
   };
-  if (cnt > 0) load(0, x, p, sv, uv);
-  for (int r = 0; r < cnt; ++r) {
-    if (r + 1 < cnt) load(r + 1, xn, pn, svn, uvn);
-    const int ss = sp == 0 ? sv : -sv;
-    const double delta = ss > 0 ? dpos : dneg;
+  auto load = [&](int r, Row &R) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) R.x[j] = xsp[r * mm + j];
+#pragma unroll
+    for (int i = 0; i < 2 * T; ++i) R.p[i] = prow[i][r * ldp];
+    R.d = dsb[r];
+    R.u = usb[r];
+  };
+  unsigned mask = 0;
+  auto step = [&](int r, const Row &R) {
+    const double delta = R.d;
     double u[2 * T];
     double ap = 0.0;
 #pragma unroll
     for (int i = 0; i < 2 * T; ++i) {
-      double t = 0.0;
+      double t = M[i][0] * R.x[0];
 #pragma unroll
-      for (int j = 0; j < T; ++j) t += M[i][j] * x[j];
+      for (int j = 1; j < T; ++j) t = fma(M[i][j], R.x[j], t);
       u[i] = sum_bc(t);
-      ap += p[i] * u[i];
+      ap = fma(R.p[i], u[i], ap);
     }
     const double a = sum_ar(ap);
     double wv[T];
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-      double t = 0.0;
+      double t = R.p[0] * M[0][j];
 #pragma unroll
-      for (int i = 0; i < 2 * T; ++i) t += p[i] * M[i][j];
+      for (int i = 1; i < 2 * T; ++i) t = fma(R.p[i], M[i][j], t);
       wv[j] = sum_ar(t);
     }
-    const double rsp = 1.0 + delta * a;
+    const double rsp = fma(delta, a, 1.0);
     const double ratio = halves_product(rsp);
-    if (uv < fabs(ratio)) {
-      const double c = delta / rsp;
+    // ratio and the uniform are identical in every lane: a scalar branch
+    if (__builtin_amdgcn_readfirstlane((int)(R.u < fabs(ratio)))) {
+      const double c = div_nr(delta, rsp);
 #pragma unroll
       for (int i = 0; i < 2 * T; ++i) {
         const double cu = c * u[i];
 #pragma unroll
-        for (int j = 0; j < T; ++j) M[i][j] -= cu * wv[j];
+        for (int j = 0; j < T; ++j) M[i][j] = fma(-cu, wv[j], M[i][j]);
       }
-      if (bc == 0) {
-#pragma unroll
-        for (int i = 0; i < 2 * T; ++i) {
-          const int aa = ar * 2 * T + i;
-          if (aa < m) prow[r * ldp + aa] = p[i] * (1.0 + delta);
-        }
-      }
-      if (lane == 0) fsb[r] = (int8_t)(-sv);
+      mask |= 1u << r;
       acc_ratio(acc, fabs(ratio));
     }
-#pragma unroll
-    for (int j = 0; j < T; ++j) x[j] = xn[j];
-#pragma unroll
-    for (int i = 0; i < 2 * T; ++i) p[i] = pn[i];
-    sv = svn;
-    uv = uvn;
+  };
+  // loads are issued one site ahead and unconditionally (a row past the end
+  // of the chunk is read again from its last row) so that waits can count
+  // exactly the loads still in flight
+  Row R0, R1;
+  const int last = cnt - 1;
+  if (cnt > 0) load(0, R0);
+  for (int r = 0; r < cnt; r += 2) {
+    load(min(r + 1, last), R1);
+    step(r, R0);
+    if (r + 1 >= cnt) break;
+    load(min(r + 2, last), R0);
+    step(r + 1, R1);
   }
+  acc.nacc += __builtin_popcount(mask);
+  return mask;
 }
 
 // LDS version for 32 < Ne <= 64: lane h of a half owns rows/columns h, h+32
 // of its spin's inverse, which stays in LDS (Ms0 / Ms1).
-__device__ void chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, int mm, double *prow, int ldp,
-                                const double *usb, int8_t *fsb, int cnt, int S, ChainAcc &acc) {
+__device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, int mm, const double *prow,
+                                    int ldp, const double *usb, const int8_t *fsb, int cnt, int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31;
   const int m = w.ne[sp];
   double *Ms = sp ? L.Ms1 : L.Ms0;
   double *wsh = L.uw + sp * 64;
   const double *xsp = xsb + sp * S * mm;
+  unsigned mask = 0;
   for (int r = 0; r < cnt; ++r) {
     const double *xrow = xsp + r * mm;
-    double *pr = prow + r * ldp;
+    const double *pr = prow + r * ldp;
     const int sv = fsb[r];
     const int ss = sp == 0 ? sv : -sv;
     const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
@@ -750,14 +754,13 @@ __device__ void chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, 
         const double cu = c * u1;
         for (int b = 0; b < m; ++b) Ms[(h + 32) * m + b] -= cu * wsh[b];
       }
-      wave_fence();
-      if (h < m) pr[h] *= 1.0 + delta;
-      if (h + 32 < m) pr[h + 32] *= 1.0 + delta;
-      if (lane == 0) fsb[r] = (int8_t)(-sv);
+      mask |= 1u << r;
       acc_ratio(acc, fabs(ratio));
+      acc.nacc += 1;
       wave_fence();
     }
   }
+  return mask;
 }
 
 // Stage chunk c (rows i0 .. i0+cnt-1) of slice l into buffer bufi: left rows
@@ -783,26 +786,54 @@ __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, 
   for (int r = TID - t0; r < cnt; r += nt) {
     L.fs[bufi * S + r] = srow[i0 + r];
     L.us[bufi * S + r] = uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)(i0 + r));
+    const int sv = srow[i0 + r];
+    L.dl[(bufi * 2 + 0) * S + r] = sv > 0 ? w.delta_dn_s : w.delta_up_s;
+    L.dl[(bufi * 2 + 1) * S + r] = -sv > 0 ? w.delta_dn_s : w.delta_up_s;
   }
 }
 
-// Write back chunk rows modified by the chain (fields; right rows when streamed).
+// Write back chunk rows after the chain: flip the accepted fields and scale
+// the accepted right rows by 1 + Delta (resident rows in place, streamed rows
+// on their way back to device memory).  The streamed loop walks the staging
+// buffer in the order stage_chunk fills it, so the same thread reads an
+// element before it is restaged.
 __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi, double *const phi[2],
                             bool resident, int mm, int t0, int nt) {
   if (TID < t0 || TID >= t0 + nt) return;
   const int S = L.S, N = w.N;
   const int cnt = min(S, N - i0);
-  if (!resident)
-    for (int sp = 0; sp < 2; ++sp) {
-      const int m = w.ne[sp];
+  const unsigned mask = (unsigned)L.iscal[8 + bufi];
+  const int8_t *fs = L.fs + bufi * S;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    auto factor = [&](int r) {
+      const int sv = fs[r];
+      const int ss = sp == 0 ? sv : -sv;
+      return 1.0 + (ss > 0 ? w.delta_dn_s : w.delta_up_s);
+    };
+    if (resident) {
+      if (mask != 0u)
+        for (int e = TID - t0; e < cnt * m; e += nt) {
+          const int r = e / m, a = e - r * m;
+          if ((mask >> r) & 1u) phi[sp][(size_t)(i0 + r) * m + a] *= factor(r);
+        }
+    } else {
       const double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
-      for (int e = TID - t0; e < cnt * m; e += nt) {
-        const int r = e / m, a = e - (e / m) * m;
-        phi[sp][(size_t)(i0 + r) * m + a] = pd[r * mm + a];
+      for (int e = TID - t0; e < cnt * mm; e += nt) {
+        const int r = e / mm, a = e - r * mm;
+        if (a < m) {
+          double v = pd[e];
+          if ((mask >> r) & 1u) v *= factor(r);
+          phi[sp][(size_t)(i0 + r) * m + a] = v;
+        }
       }
     }
+  }
   int8_t *srow = w.s + (size_t)(l - 1) * N;
-  for (int r = TID - t0; r < cnt; r += nt) srow[i0 + r] = L.fs[bufi * S + r];
+  for (int r = TID - t0; r < cnt; r += nt) {
+    const int8_t f = fs[r];
+    srow[i0 + r] = ((mask >> r) & 1u) ? (int8_t)(-f) : f;
+  }
 }
 
 // All slices of block k with the inverse held by wave 0.  On entry D_{l0} has
@@ -850,10 +881,12 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
             prow = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
             ldp = mm;
           }
+          unsigned mask;
           if constexpr (T > 0)
-            chain_chunk_reg<T>(w, M, xsb, mm, prow, ldp, L.us + bufi * S, L.fs + bufi * S, cnt, S, acc);
+            mask = chain_chunk_reg<T>(w, M, xsb, mm, prow, ldp, L.us + bufi * S, L.dl + bufi * 2 * S, cnt, S, acc);
           else
-            chain_chunk_lds(w, L, xsb, mm, prow, ldp, L.us + bufi * S, L.fs + bufi * S, cnt, S, acc);
+            mask = chain_chunk_lds(w, L, xsb, mm, prow, ldp, L.us + bufi * S, L.fs + bufi * S, cnt, S, acc);
+          if (TID == 0) L.iscal[8 + bufi] = (int)mask;
         } else {
           if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
           if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);

@@ -48,6 +48,9 @@ CASES = {
     "square4_U0": (lambda: W.square_lattice(4), dict(U=0.0, beta=1.0, dtau=0.1, n_stab=5, n_up=2, n_dn=3)),
     "square4_nstab1": (lambda: W.square_lattice(4), dict(U=4.0, beta=0.4, dtau=0.1, n_stab=1, n_up=2, n_dn=2)),
     "square8_ne12": (lambda: W.square_lattice(8), dict(U=4.0, beta=1.0, dtau=0.1, n_stab=10, n_up=12, n_dn=12)),
+    # 16 < Ne <= 32 (widest register tile) and Ne > 32 (inverse kept in LDS)
+    "square6_ne20": (lambda: W.square_lattice(6), dict(U=4.0, beta=0.6, dtau=0.1, n_stab=3, n_up=20, n_dn=17)),
+    "chain40_ne34": (lambda: W.periodic_chain(40), dict(U=2.0, beta=0.4, dtau=0.1, n_stab=2, n_up=34, n_dn=5)),
 }
 
 
@@ -86,7 +89,7 @@ def test_log_weight(lq, ctx, name):
 
 
 @pytest.mark.parametrize("name", ["square4_u4", "pchain6_ragged", "flat4", "square6_ne5", "square4_empty_dn",
-                                  "chain4_full_up", "square8_ne12"])
+                                  "chain4_full_up", "square8_ne12", "square6_ne20", "chain40_ne34"])
 def test_green(lq, ctx, name):
     lat, par, g, o = _pair(lq, ctx, name)
     for b in sorted({0, 1, par.n_stab, min(par.n_stab + 3, par.L_tau), par.L_tau}):
@@ -96,7 +99,7 @@ def test_green(lq, ctx, name):
 
 
 @pytest.mark.parametrize("name", ["square4_u4", "pchain6_ragged", "chain5_open", "flat4", "square6_ne5",
-                                  "square4_empty_dn", "square8_ne12"])
+                                  "square4_empty_dn", "square8_ne12", "square6_ne20", "chain40_ne34"])
 def test_flip_ratio(lq, ctx, name):
     lat, par, g, o = _pair(lq, ctx, name)
     rng = np.random.default_rng(7)
