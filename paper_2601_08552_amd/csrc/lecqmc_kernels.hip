@@ -124,6 +124,13 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full barrier waits for every outstanding load).
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ double wg_sum(double v, double *red) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
@@ -150,6 +157,9 @@ __device__ double wg_max(double v, double *red) {
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) int8_t lds_i8;
 __device__ __forceinline__ lds_f64 *as_lds(double *p) { return (lds_f64 *)p; }
+// barrier after a pass over X: LDS-only when X lives in LDS
+template <typename P> struct PassSync { __device__ static void run() { SYNC(); } };
+template <> struct PassSync<lds_f64 *> { __device__ static void run() { lds_sync(); } };
 __device__ __forceinline__ const lds_f64 *as_lds(const double *p) { return (const lds_f64 *)p; }
 __device__ __forceinline__ lds_i8 *as_lds(int8_t *p) { return (lds_i8 *)p; }
 
@@ -238,7 +248,7 @@ __device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc
         X[jj[u]] = o[u] * xi[u] + d[u] * xj[u];
       }
   }
-  SYNC();
+  PassSync<P>::run();
 }
 
 template <typename P>
@@ -250,7 +260,7 @@ __device__ __forceinline__ void diag_t(const WalkerDesc &w, P X, int m, int l, i
     if (inverse) f = 1.0 / f;
     for (int a = 0; a < m; ++a) X[(size_t)i * m + a] *= f;
   }
-  SYNC();
+  PassSync<P>::run();
 }
 
 __device__ __forceinline__ bool in_lds(const void *p) {
@@ -1387,6 +1397,42 @@ __device__ __forceinline__ int perm_col(int c, int k, int ne) {
   return c < k ? c : (c < ne - 1 ? c + 1 : k);
 }
 
+// Fast path of the column propagation in the addition move: the vector lives
+// in LDS and every thread owns at most kFq of its sites (i = TID + q kThreads),
+// with their onsite factors cached; the fields of the next slice are loaded
+// while the current one is applied, and only LDS barriers are used so that
+// loads issued before the call (the level's Q rows) stay in flight.
+constexpr int kFq = 4;   // sites per thread on the fast path (N <= 1024)
+constexpr int kFne = 8;  // Q columns cached in registers (Ne <= 8)
+__device__ __forceinline__ void fock_propagate(const WalkerDesc &w, int sp, double *fw, int l0, int l1,
+                                               const double (&eps)[kFq], const Lds &L) {
+  const int N = w.N;
+  lds_f64 *v = as_lds(fw);
+  int fc[kFq], fn[kFq];
+  auto fields = [&](int l, int (&f)[kFq]) {
+    const int8_t *srow = w.s + (size_t)(l - 1) * N;
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      const int i = TID + q * kThreads;
+      f[q] = i < N ? srow[i] : 1;
+    }
+  };
+  fields(l0, fc);
+  for (int l = l0; l <= l1; ++l) {
+    if (l < l1) fields(l + 1, fn);
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      const int i = TID + q * kThreads;
+      const int ss = sp == 0 ? fc[q] : -fc[q];
+      if (i < N) v[i] *= (ss > 0 ? w.elam : w.emlam) * eps[q];
+    }
+    lds_sync();
+    apply_ek(w, L, fw, 1);
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) fc[q] = fn[q];
+  }
+}
+
 // returns accepted (uniform); *log_abs_r / *sign_r in scal
 __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc, bool commit,
                           Lds &L, double *fw, double *ratio_out) {
@@ -1494,18 +1540,67 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
   if (L.scal[22] == 0.0) {
     for (int i = TID; i < N; i += kThreads) fw[i] = (i == j) ? 1.0 : 0.0;
     SYNC();
+    const bool fast = in_lds(fw) && N <= kFq * kThreads;
+    const bool qcache = fast && ne <= kFne;
+    double eps_r[kFq];
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      const int i = TID + q * kThreads;
+      eps_r[q] = (fast && i < N) ? w.eps_fac[i] : 1.0;
+    }
     for (int lvl = 0; lvl < n; ++lvl) {
       const int l0 = lvl * w.nstab + 1, l1 = min((lvl + 1) * w.nstab, w.L);
-      for (int l = l0; l <= l1; ++l) {
-        apply_diag(w, fw, 1, l, sp, false);
-        apply_ek(w, L, fw, 1);
-      }
       const double *Q = w.RQ[sp] + (size_t)lvl * N * ne;
+      // the level's Q rows of this thread's sites, loaded under the propagation
+      double qr[kFq][kFne];
+      if (qcache) {
+#pragma unroll
+        for (int q = 0; q < kFq; ++q) {
+          const int i = TID + q * kThreads;
+#pragma unroll
+          for (int a = 0; a < kFne; ++a) qr[q][a] = (i < N && a < ne) ? Q[(size_t)i * ne + a] : 0.0;
+        }
+      }
+      if (fast) {
+        fock_propagate(w, sp, fw, l0, l1, eps_r, L);
+      } else {
+        for (int l = l0; l <= l1; ++l) {
+          apply_diag(w, fw, 1, l, sp, false);
+          apply_ek(w, L, fw, 1);
+        }
+      }
       const double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
       for (int a = TID; a < 64; a += kThreads) vsum[a] = 0.0;
       SYNC();
       for (int pass = 0; pass < 2 && m > 0; ++pass) {
-        gram(Q, ne, fw, 1, N, y, L.red);  // y = Q^T w
+        if (qcache) {
+          // y = Q^T w: per-thread partial sums over own rows, then a block sum
+          double yp[kFne];
+#pragma unroll
+          for (int a = 0; a < kFne; ++a) yp[a] = 0.0;
+#pragma unroll
+          for (int q = 0; q < kFq; ++q) {
+            const int i = TID + q * kThreads;
+            const double f = i < N ? fw[i] : 0.0;
+#pragma unroll
+            for (int a = 0; a < kFne; ++a) yp[a] += qr[q][a] * f;
+          }
+#pragma unroll
+          for (int a = 0; a < kFne; ++a) {
+            double v = yp[a];
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            yp[a] = v;
+          }
+          if ((TID & 63) == 0)
+#pragma unroll
+            for (int a = 0; a < kFne; ++a) L.red[(TID >> 6) * kFne + a] = yp[a];
+          SYNC();
+          if (TID < ne)
+            y[TID] = (L.red[TID] + L.red[kFne + TID]) + (L.red[2 * kFne + TID] + L.red[3 * kFne + TID]);
+          SYNC();
+        } else {
+          gram(Q, ne, fw, 1, N, y, L.red);  // y = Q^T w
+        }
         if (TID == 0) {
           for (int r = k; r <= ne - 2; ++r) {
             const double a = y[r], b = y[r + 1];
@@ -1521,10 +1616,22 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
           }
         }
         SYNC();
-        for (int i = TID; i < N; i += kThreads) {
-          double s = 0.0;
-          for (int a = 0; a < ne; ++a) s += Q[(size_t)i * ne + a] * z[a];
-          fw[i] -= s;
+        if (qcache) {
+#pragma unroll
+          for (int q = 0; q < kFq; ++q) {
+            const int i = TID + q * kThreads;
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < kFne; ++a)
+              if (a < ne) s += qr[q][a] * z[a];
+            if (i < N) fw[i] -= s;
+          }
+        } else {
+          for (int i = TID; i < N; i += kThreads) {
+            double s = 0.0;
+            for (int a = 0; a < ne; ++a) s += Q[(size_t)i * ne + a] * z[a];
+            fw[i] -= s;
+          }
         }
         SYNC();
       }
