@@ -1125,7 +1125,7 @@ __device__ void inverse_at_beta(const WalkerDesc &w, int sp, Lds &L, double *log
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *descs, int draw_fields, int draw_occ) {
+__global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *__restrict__ descs, int draw_fields, int draw_occ) {
   const WalkerDesc &w = descs[blockIdx.x];
   if (draw_fields) {
     const int tot = w.L * w.N;
@@ -1153,7 +1153,7 @@ __global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *descs, int 
 }
 
 // Fresh log-weight from the current (eta, s): right stack + inverse at beta.
-__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *descs, LdsPlan pl, int set_tracked) {
+__global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *__restrict__ descs, LdsPlan pl, int set_tracked) {
   const WalkerDesc &w = descs[blockIdx.x];
   Lds L = carve(pl);
   load_bonds(w, L, pl.bond_words);
@@ -1184,7 +1184,7 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *des
 // Y <- E_K^T Y, store X'_l = Y (the left state at the flip point of slice l,
 // (Phi_L(l) E_K)^T), Y <- D_l Y; at every block boundary a thin QR, LS[k-1] = Q.
 // LS[n] = P.  Y stays in LDS when it fits.
-__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs, LdsPlan pl) {
+__global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   Lds L = carve(pl);
   load_bonds(w, L, pl.bond_words);
@@ -1212,7 +1212,7 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *descs
 // block ends (push (Q_k, V_k)), wrap check and measurements at interior
 // boundaries, and the fresh weight and inverse at tau = beta.
 template <int TSEL>
-__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, LdsPlan pl, int want_aw) {
+__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restrict__ descs, LdsPlan pl, int want_aw) {
   const WalkerDesc &w = descs[blockIdx.x];
   Lds L = carve(pl);
   const int mm = pl.mm < 1 ? 1 : pl.mm;
@@ -1304,7 +1304,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *descs, L
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int meas_slots(const WalkerDesc &w) { return w.nblk > 1 ? w.nblk - 1 : 1; }
 
-__global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *descs, LdsPlan pl, int slots) {
+__global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *__restrict__ descs, LdsPlan pl, int slots) {
   const WalkerDesc &w = descs[blockIdx.x / slots];
   const int q = blockIdx.x % slots;
   if (q >= meas_slots(w)) return;
@@ -1367,7 +1367,7 @@ __global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *descs, L
   if (TID == 0) part[w.nobs] = wrap;
 }
 
-__global__ void __launch_bounds__(kThreads) k_measure_sum(const WalkerDesc *descs) {
+__global__ void __launch_bounds__(kThreads) k_measure_sum(const WalkerDesc *__restrict__ descs) {
   const WalkerDesc &w = descs[blockIdx.x];
   const int slots = meas_slots(w);
   const size_t rec = (size_t)w.nobs + 1;
@@ -1785,7 +1785,7 @@ __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
 
 // One workgroup per (walker, spin): the two species have separate stacks,
 // inverses and occupations, so their swap sequences are independent.
-__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *descs, LdsPlan pl) {
+__global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   const int sp = blockIdx.x & 1;
   Lds L = carve(pl);
@@ -1835,7 +1835,7 @@ __device__ void left_state(const WalkerDesc &w, int sp, int b, Lds &L) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *descs, int mm, int b, int sp, double *G) {
+__global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *__restrict__ descs, int mm, int b, int sp, double *G) {
   const WalkerDesc &w = descs[0];
   Lds L = carve(mm, 0);
   const int N = w.N, m = w.ne[sp];
@@ -1861,7 +1861,7 @@ __global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *descs, int
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *descs, int mm, int slice, int site) {
+__global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *__restrict__ descs, int mm, int slice, int site) {
   const WalkerDesc &w = descs[0];
   Lds L = carve(mm, 0);
   const int N = w.N, l = slice + 1;
@@ -1891,7 +1891,7 @@ __global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *descs
   if (TID == 0) w.dbg[0] = r;
 }
 
-__global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *descs, int mm, int sp, int k, int j) {
+__global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *__restrict__ descs, int mm, int sp, int k, int j) {
   const WalkerDesc &w = descs[0];
   Lds L = carve(mm, 0);
   for (int s2 = 0; s2 < 2; ++s2) {
