@@ -8,7 +8,9 @@ walker: left-stack build, forward pass with N * L_tau Ising-flip attempts and
 QR stabilisation, and N_sigma particle-hole swaps per spin.
 
 Prints one JSON line.  value = HS-field updates per second (flip attempts of
-all walkers / wall time of the timed sweeps, inputs already resident).
+all walkers / wall time of the timed sweeps, inputs already resident) of the
+all-FP64 path; the "mixed" object gives the same measurement with the slice
+propagation in FP32 (QR, inverses, ratios and weights FP64) and its error.
 """
 from __future__ import annotations
 
@@ -96,8 +98,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--walkers", type=int, default=N_WALKERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--cpu-sweeps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -111,33 +114,50 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = lecqmc.Context(0, stream=stream)
-    walkers = []
-    for s in range(args.walkers):
-        lat, par = W.config_dilute(seed=s + 1, walker_id=s)
-        walkers.append(lecqmc.Walker(ctx, lat, par))
+
+    def run(precision):
+        """Timed batched sweeps of the workload at one precision."""
+        walkers = []
+        for s in range(args.walkers):
+            lat, par = W.config_dilute(seed=s + 1, walker_id=s, precision=precision)
+            walkers.append(lecqmc.Walker(ctx, lat, par))
+        for _ in range(args.warmup):
+            lecqmc.sweep_batch(walkers, 1)
+        ctx.synchronize()
+        ctx.set_timing(True)
+        ctx.phase_times()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for k in range(args.steps):
+            lecqmc.sweep_batch(walkers, 1)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_phase, cnt = ctx.phase_times()
+        ctx.set_timing(False)
+        step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+        # weight carried by the chain vs the FP64 fresh recomputation, walker 0
+        lt, _ = walkers[0].tracked_weight()
+        lf, _ = walkers[0].log_weight()
+        res = dict(wall=wall, ms_phase=ms_phase, cnt=cnt, step_ms=step_ms, stats=walkers[0].stats(),
+                   logw_rel_err=abs(lt - lf) / max(1.0, abs(lf)), lat=lat, par=par)
+        for w in walkers:
+            w.close()
+        return res
+
+    r64 = run(lecqmc.FP64)
+    rmx = None if args.no_mixed else run(lecqmc.MIXED)
+    lat, par = r64["lat"], r64["par"]
     N, L = lat.n_sites, par.L_tau
-    for _ in range(args.warmup):
-        lecqmc.sweep_batch(walkers, 1)
-    ctx.synchronize()
-    ctx.set_timing(True)
-    ctx.phase_times()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(args.steps):
-        lecqmc.sweep_batch(walkers, 1)
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_phase, cnt = ctx.phase_times()
-    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    wall, ms_phase, cnt, step_ms = r64["wall"], r64["ms_phase"], r64["cnt"], r64["step_ms"]
     updates = args.walkers * N * L * args.steps
     value = updates / wall
     fwd_ms = ms_phase[1] / max(cnt[1], 1)
     alg = algorithmic_bytes_forward(N, par.n_up, par.n_dn, L, par.n_stab) * args.walkers
     achieved = alg / (fwd_ms * 1e-3) / 1e9
-    st = walkers[0].stats()
+    st = r64["stats"]
     traffic = measured_traffic(os.path.join(ROOT, "paper_2601_08552_amd", "csrc", "lecqmc_kernels.hip"),
                                os.path.join(ROOT, "profiles", "k_forward_dilute32x32_64w_pmc.json"))
     out = {
@@ -162,13 +182,29 @@ def main():
                                 "fock": ms_phase[2] / max(cnt[2], 1)},
         "accuracy": {"vs_oracle": "bit-identical Markov chain; log-weight, Green's function and ratios "
                                   "within 1e-10 relative (parity tests)",
-                     "logw_drift": st["logw_drift"], "max_wrap_err": st["max_wrap_err"]},
+                     "logw_drift": st["logw_drift"], "max_wrap_err": st["max_wrap_err"],
+                     "logw_rel_err_vs_fresh_fp64": r64["logw_rel_err"]},
         "roofline": {"bound": "hbm", "kernel": "k_forward", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg,
                      "note": "bound in practice by the dependent flip chain: %.1f ns per site per walker"
                              % (fwd_ms * 1e6 / (N * L))},
     }
+    if rmx is not None:
+        mp_ = rmx["ms_phase"]
+        mc_ = rmx["cnt"]
+        out["mixed"] = {
+            "value": updates / rmx["wall"], "unit": "HS-field updates/s", "ms_per_step": rmx["wall"] * 1e3 / args.steps,
+            "dtype": "f32 propagation / f64 QR, inverses, ratios, weights",
+            "latency_ms": {"p50": float(np.percentile(rmx["step_ms"], 50)),
+                           "p99": float(np.percentile(rmx["step_ms"], 99))},
+            "phase_ms_per_launch": {"left_stack": mp_[0] / max(mc_[0], 1), "forward": mp_[1] / max(mc_[1], 1),
+                                    "fock": mp_[2] / max(mc_[2], 1)},
+            "accuracy": {"logw_rel_err_vs_fresh_fp64": rmx["logw_rel_err"],
+                         "logw_drift": rmx["stats"]["logw_drift"],
+                         "vs_oracle": "first sweep of the 32x32 workload: identical fields and log|W| within "
+                                      "1e-5 relative; estimators within 1e-4 (mixed parity tests)"},
+        }
     if not args.no_cpu_baseline:
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(procs, args.cpu_sweeps)

@@ -50,6 +50,12 @@ extern "C" {
 #define LECQMC_ESTATE (-5)    /* call not valid in the walker's state                 */
 
 #define LECQMC_FP64 0         /* all arithmetic in FP64                               */
+#define LECQMC_MIXED 1        /* mixed precision: the slice propagation (Slater blocks,
+                                 stored left states, Fock columns: E_K and D_l) is
+                                 stored and computed in FP32 between stabilisations;
+                                 QR and Gram matrices, Ne x Ne inverses and
+                                 determinants, log-weights, flip and swap ratios
+                                 and the right stack stay FP64                    */
 #define LECQMC_NO_FOCK 1      /* flags: skip the particle-hole swap phase             */
 #define LECQMC_NO_FLIPS 2     /* flags: skip the Ising flips (fields frozen)          */
 
@@ -73,7 +79,7 @@ typedef struct {
   int32_t n_stab;           /* slices per QR stabilisation, >= 1              */
   int32_t n_up, n_dn;       /* 0..min(n_sites, LECQMC_MAX_NE)                 */
   uint64_t seed, walker_id; /* key of the counter-based generator             */
-  int32_t precision;        /* LECQMC_FP64                                    */
+  int32_t precision;        /* LECQMC_FP64 or LECQMC_MIXED                    */
   int32_t flags;            /* LECQMC_NO_FOCK | LECQMC_NO_FLIPS               */
   double wrap_tol;          /* max |A_wrap - A_fresh| diagonal (<= 0: 1e-8)   */
 } lecqmc_params;
@@ -102,7 +108,9 @@ int lecqmc_ctx_set_timing(lecqmc_ctx *ctx, int32_t enable);
 int lecqmc_ctx_phase_times(lecqmc_ctx *ctx, double ms[3], int64_t counts[3]);
 
 /* Device bytes one walker needs (right and left stacks dominate:
- * 2 * (2 n + 1 + L_tau) * N * Ne * 8 bytes); 0 if the input is invalid. */
+ * 2 * (2 n + 1) * N * Ne * 8 bytes plus the stored left states,
+ * 2 * L_tau * N * Ne * 8 bytes, or * 4 bytes with LECQMC_MIXED); 0 if the
+ * input is invalid. */
 size_t lecqmc_footprint_bytes(const lecqmc_lattice *lat, const lecqmc_params *par);
 
 /* Create a walker: copies the lattice, builds the model tables, draws the
@@ -119,10 +127,12 @@ int lecqmc_destroy_walker(lecqmc_walker *w);
  * interior stabilisation boundaries (tau = beta when there is one block). */
 int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measure);
 /* The same for n walkers of one context in one launch per phase; shapes
- * may differ between walkers. */
+ * may differ between walkers.  FP64 and mixed-precision walkers may be
+ * combined: each precision gets its own launch per phase. */
 int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure);
 
-/* Fresh log|W| and sign from the current (eta, s) (right chain + QR). */
+/* Fresh log|W| and sign from the current (eta, s) (right chain + QR, FP64
+ * whatever the walker's precision). */
 int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);
 /* Weight carried by the chain (updated by every accepted move, reset to the
  * fresh value at tau = beta of each sweep). */

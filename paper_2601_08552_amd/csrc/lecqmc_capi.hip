@@ -79,7 +79,9 @@ extern "C" const char *lecqmc_last_error(void) { return g_err; }
 // fixed layout.
 struct LaunchCfg {
   LdsPlan fwd, left, fock, meas;
+  LdsPlan fresh;  // FP64 right chain of the fresh weight (all walkers)
   int slots;
+  int mixed;      // FP32 storage in the sweep phases
 };
 
 static LdsPlan plan_for(int mm, long phi_need, int bond_need, bool staged_if_streamed) {
@@ -96,23 +98,29 @@ static LdsPlan plan_for(int mm, long phi_need, int bond_need, bool staged_if_str
   return p;
 }
 
+// Walkers of one launch share a precision (the sweep launchers group them).
+// Resident blocks are counted in doubles: FP32 storage needs half of them.
 static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
   int mm = 1, bonds = 0, slots = 1;
-  long fwd = 0, left = 0, fock = 0;
+  long fwd = 0, left = 0, fock = 0, fresh = 0;
   bool compact = true;
+  const int mixed = n > 0 ? ws[0]->h.mixed : 0;
+  auto in_doubles = [&](long entries) { return mixed ? (entries + 1) / 2 : entries; };
   for (int t = 0; t < n; ++t) {
     const lecqmc_walker *w = ws[t];
     mm = std::max(mm, w->mmax);
-    fwd = std::max(fwd, (long)w->N * (w->ne[0] + w->ne[1]));
-    left = std::max(left, (long)w->N * std::max(w->ne[0], w->ne[1]));
-    fock = std::max(fock, (long)w->N);
+    fwd = std::max(fwd, in_doubles((long)w->N * (w->ne[0] + w->ne[1])));
+    left = std::max(left, in_doubles((long)w->N * std::max(w->ne[0], w->ne[1])));
+    fock = std::max(fock, in_doubles((long)w->N));
+    fresh = std::max(fresh, (long)w->N * std::max(w->ne[0], w->ne[1]));
     if (w->h.ncoef == 0) compact = false;
     bonds = std::max(bonds, w->h.bond_words);
     slots = std::max(slots, w->nblk - 1);
   }
   if (!compact) bonds = 0;
-  return {plan_for(mm, fwd, bonds, true), plan_for(mm, left, bonds, false), plan_for(mm, fock, bonds, false),
-          LdsPlan{mm, 0, 0, 0}, slots};
+  return {plan_for(mm, fwd, bonds, true),  plan_for(mm, left, bonds, false), plan_for(mm, fock, bonds, false),
+          LdsPlan{mm, 0, 0, 0},            plan_for(mm, fresh, bonds, false), slots,
+          mixed};
 }
 
 // ---------------------------------------------------------------------------
@@ -132,7 +140,8 @@ static int validate(const lecqmc_lattice *lat, const lecqmc_params *par, int *L_
   if (par->n_stab <= 0) return fail(LECQMC_EINVAL, "n_stab must be >= 1");
   if (!(par->dtau > 0.0) || !(par->beta > 0.0)) return fail(LECQMC_EINVAL, "beta and dtau must be > 0");
   if (!(par->U >= 0.0)) return fail(LECQMC_EINVAL, "U must be >= 0 (spin-channel decoupling)");
-  if (par->precision != LECQMC_FP64) return fail(LECQMC_EINVAL, "unsupported precision %d", par->precision);
+  if (par->precision != LECQMC_FP64 && par->precision != LECQMC_MIXED)
+    return fail(LECQMC_EINVAL, "unsupported precision %d", par->precision);
   const double Lf = par->beta / par->dtau;
   const long L = lround(Lf);
   if (L <= 0 || fabs(Lf - (double)L) > 1e-9 * (Lf > 1 ? Lf : 1)) return fail(LECQMC_EINVAL, "beta/dtau not integral");
@@ -178,7 +187,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int obs_count(int N, int ns) { return 8 + 2 * ns * ns + (N <= 64 ? 2 * N * N + 2 * N : 0); }
 
-static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int ncol, int ns) {
+static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int ncol, int ns, int mixed) {
   Plan p;
   const int nb = (L + nstab - 1) / nstab;
   const int mmax = std::max(1, std::max(ne0, ne1));
@@ -192,7 +201,7 @@ static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int
   for (int s = 0; s < 2; ++s) {
     const size_t blk = (size_t)N * ne[s] * sizeof(double);
     p.off_LS[s] = take(blk * (nb + 1));
-    p.off_LX[s] = take(blk * L);
+    p.off_LX[s] = take((size_t)N * ne[s] * (mixed ? sizeof(float) : sizeof(double)) * L);
     p.off_RQ[s] = take(blk * nb);
     p.off_RV[s] = take(sizeof(double) * (size_t)ne[s] * ne[s] * nb);
     p.off_Minv[s] = take(sizeof(double) * (size_t)ne[s] * ne[s]);
@@ -237,7 +246,9 @@ extern "C" size_t lecqmc_footprint_bytes(const lecqmc_lattice *lat, const lecqmc
   int L = 0;
   if (validate(lat, par, &L)) return 0;
   const int ns = (lat->sublattice && lat->n_sublattices > 0) ? lat->n_sublattices : 1;
-  return make_plan(lat->n_sites, L, par->n_stab, par->n_up, par->n_dn, lat->n_bonds, lat->n_colors, ns).total;
+  return make_plan(lat->n_sites, L, par->n_stab, par->n_up, par->n_dn, lat->n_bonds, lat->n_colors, ns,
+                   par->precision == LECQMC_MIXED)
+      .total;
 }
 
 // ---------------------------------------------------------------------------
@@ -342,7 +353,8 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
       used[g[a]] = 1;
     }
   }
-  const Plan p = make_plan(N, L, par->n_stab, ne[0], ne[1], lat->n_bonds, lat->n_colors, ns);
+  const Plan p = make_plan(N, L, par->n_stab, ne[0], ne[1], lat->n_bonds, lat->n_colors, ns,
+                           par->precision == LECQMC_MIXED);
   if (ctx->budget && ctx->used + p.total > ctx->budget)
     return fail(LECQMC_ENOMEM, "walker needs %zu bytes, %zu of %zu in use", p.total, ctx->used, ctx->budget);
   HIPCHK(hipSetDevice(ctx->device));
@@ -367,6 +379,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   memset(&d, 0, sizeof d);
   d.N = N; d.L = L; d.nstab = par->n_stab; d.nblk = w->nblk; d.ncol = lat->n_colors; d.nbonds = lat->n_bonds;
   d.nsub = ns; d.ncells = lat->n_cells > 0 ? lat->n_cells : N; d.flags = par->flags; d.nobs = w->nobs;
+  d.mixed = par->precision == LECQMC_MIXED ? 1 : 0;
   d.ne[0] = ne[0]; d.ne[1] = ne[1]; d.mmax = w->mmax;
   d.seed = par->seed; d.wid = par->walker_id;
   // Ising decoupling in the spin channel: cosh(lambda) = exp(dtau U / 2)
@@ -492,7 +505,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   const int draw_occ = (occ_up ? 0 : 1) | (occ_dn ? 0 : 2);
   if (!fields || draw_occ) e = launch_init(w->d_desc, fields ? 0 : 1, draw_occ, ctx->stream);
   const LaunchCfg cf = launch_cfg(&w, 1);
-  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, cf.left, 1, ctx->stream);
+  if (e == hipSuccess) e = launch_fresh_weight(w->d_desc, 1, cf.fresh, 1, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return cleanup(fail(LECQMC_EDEVICE, "init: %s", hipGetErrorString(e)));
   ctx->used += p.total;
@@ -521,10 +534,10 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
   lecqmc_ctx *c = w->ctx;
   const LaunchCfg cf = launch_cfg(&w, 1);
   for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.left, st); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.fwd, do_measure, st); }));
+    HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.left, cf.mixed, st); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.fwd, do_measure, cf.mixed, st); }));
     if (do_measure) HIPCHK(launch_measure(w->d_desc, 1, std::max(1, w->nblk - 1), cf.meas, st));
-    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.fock, st); }));
+    HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.fock, cf.mixed, st); }));
   }
   return 0;
 }
@@ -532,10 +545,18 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
 extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure) {
   if (!ws || n <= 0 || n_sweeps < 0) return fail(LECQMC_EINVAL, "bad arguments");
   lecqmc_ctx *c = ws[0]->ctx;
+  // FP64 walkers first, then mixed-precision ones: one launch per group and phase
+  std::vector<lecqmc_walker *> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int t = 0; t < n; ++t) {
+      if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers of a batch must share one context");
+      if (ws[t]->h.mixed == pass) order.push_back(ws[t]);
+    }
   std::vector<WalkerDesc> hd(n);
+  int n64 = 0;
   for (int t = 0; t < n; ++t) {
-    if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers of a batch must share one context");
-    hd[t] = ws[t]->h;
+    hd[t] = order[t]->h;
+    n64 += order[t]->h.mixed ? 0 : 1;
   }
   HIPCHK(hipSetDevice(c->device));
   if (c->batch_cap < n) {
@@ -546,12 +567,30 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
-  const LaunchCfg cf = launch_cfg(ws, n);
+  struct Group {
+    const WalkerDesc *d;
+    int n;
+    LaunchCfg cf;
+  };
+  std::vector<Group> groups;
+  if (n64 > 0) groups.push_back({c->d_batch, n64, launch_cfg(order.data(), n64)});
+  if (n > n64) groups.push_back({c->d_batch + n64, n - n64, launch_cfg(order.data() + n64, n - n64)});
+  auto each = [&](auto &&launch) {
+    for (const Group &g : groups) {
+      const hipError_t e = launch(g);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return launch_left_stack(c->d_batch, n, cf.left, c->stream); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(c->d_batch, n, cf.fwd, do_measure, c->stream); }));
-    if (do_measure) HIPCHK(launch_measure(c->d_batch, n, cf.slots, cf.meas, c->stream));
-    HIPCHK(timed(c, 2, [&] { return launch_fock(c->d_batch, n, cf.fock, c->stream); }));
+    HIPCHK(timed(c, 0, [&] { return each([&](const Group &g) {
+      return launch_left_stack(g.d, g.n, g.cf.left, g.cf.mixed, c->stream); }); }));
+    HIPCHK(timed(c, 1, [&] { return each([&](const Group &g) {
+      return launch_forward(g.d, g.n, g.cf.fwd, do_measure, g.cf.mixed, c->stream); }); }));
+    if (do_measure)
+      HIPCHK(each([&](const Group &g) { return launch_measure(g.d, g.n, g.cf.slots, g.cf.meas, c->stream); }));
+    HIPCHK(timed(c, 2, [&] { return each([&](const Group &g) {
+      return launch_fock(g.d, g.n, g.cf.fock, g.cf.mixed, c->stream); }); }));
   }
   return 0;
 }
@@ -560,7 +599,7 @@ extern "C" int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *s
   if (!w || !log_abs_w || !sign) return fail(LECQMC_EINVAL, "null argument");
   HIPCHK(hipSetDevice(w->ctx->device));
   const LaunchCfg cf = launch_cfg(&w, 1);
-  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.left, 0, w->ctx->stream));
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.fresh, 0, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
   HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
@@ -657,7 +696,7 @@ extern "C" int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const in
   sc.sweep = sweep_counter;
   HIPCHK(hipMemcpy(w->h.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
   const LaunchCfg cf = launch_cfg(&w, 1);
-  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.left, 1, w->ctx->stream));
+  HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.fresh, 1, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   return check_status(w);
 }

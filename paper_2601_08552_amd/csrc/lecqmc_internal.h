@@ -32,6 +32,7 @@ struct Scalars {
 // Device descriptor of one walker (copied to device memory at creation).
 struct WalkerDesc {
   int N, L, nstab, nblk, ncol, nbonds, nsub, ncells, flags, nobs;
+  int mixed;                    // 1: FP32 slice propagation (LECQMC_MIXED)
   int ne[2];
   int mmax;                     // max(ne[0], ne[1], 1): stride of the per-level Fock scratch
   uint64_t seed, wid;
@@ -55,6 +56,7 @@ struct WalkerDesc {
   int *occ[2];                  // [N] each (first ne used)
   double *LS[2];                // [(nblk + 1)][N][ne]  left states at block boundaries
   double *LX[2];                // [L][N][ne]  left state at the flip point of every slice
+                                // (FP32 entries for mixed-precision walkers)
   double *RQ[2];                // [nblk][N][ne]
   double *RV[2];                // [nblk][ne][ne]
   double *Minv[2];              // [ne][ne]
@@ -91,9 +93,11 @@ size_t lds_bytes(const LdsPlan &p);
 // kernel launchers (lecqmc_kernels.hip); descs = device array of descriptors.
 hipError_t launch_init(const WalkerDesc *d_desc, int draw_fields, int draw_occ, hipStream_t st);
 hipError_t launch_fresh_weight(const WalkerDesc *d_descs, int n, LdsPlan p, int set_tracked, hipStream_t st);
-hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, LdsPlan p, hipStream_t st);
-hipError_t launch_forward(const WalkerDesc *d_descs, int n, LdsPlan p, int do_measure, hipStream_t st);
-hipError_t launch_fock(const WalkerDesc *d_descs, int n, LdsPlan p, hipStream_t st);
+// mixed != 0: FP32 storage and propagation of the Slater blocks, stored left
+// states and Fock columns (every walker of the launch must be mixed)
+hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, LdsPlan p, int mixed, hipStream_t st);
+hipError_t launch_forward(const WalkerDesc *d_descs, int n, LdsPlan p, int do_measure, int mixed, hipStream_t st);
+hipError_t launch_fock(const WalkerDesc *d_descs, int n, LdsPlan p, int mixed, hipStream_t st);
 hipError_t launch_measure(const WalkerDesc *d_descs, int n, int slots, LdsPlan p, hipStream_t st);
 hipError_t launch_green(const WalkerDesc *d_desc, int max_ne, int boundary, int spin, double *G, hipStream_t st);
 hipError_t launch_flip_ratio(const WalkerDesc *d_desc, int max_ne, int slice, int site, hipStream_t st);

@@ -155,12 +155,20 @@ __device__ double wg_max(double v, double *red) {
 // pointers, so the bond-table loads are not ordered behind LDS stores).
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(3))) int8_t lds_i8;
 __device__ __forceinline__ lds_f64 *as_lds(double *p) { return (lds_f64 *)p; }
+__device__ __forceinline__ lds_f32 *as_lds(float *p) { return (lds_f32 *)p; }
 // barrier after a pass over X: LDS-only when X lives in LDS
 template <typename P> struct PassSync { __device__ static void run() { SYNC(); } };
 template <> struct PassSync<lds_f64 *> { __device__ static void run() { lds_sync(); } };
+template <> struct PassSync<lds_f32 *> { __device__ static void run() { lds_sync(); } };
+// arithmetic type of a pass over storage P: FP32 storage is propagated in FP32
+template <typename P> struct Elem { using T = double; };
+template <> struct Elem<float *> { using T = float; };
+template <> struct Elem<lds_f32 *> { using T = float; };
 __device__ __forceinline__ const lds_f64 *as_lds(const double *p) { return (const lds_f64 *)p; }
+__device__ __forceinline__ const lds_f32 *as_lds(const float *p) { return (const lds_f32 *)p; }
 __device__ __forceinline__ lds_i8 *as_lds(int8_t *p) { return (lds_i8 *)p; }
 
 typedef __attribute__((address_space(3))) int lds_i32;
@@ -218,13 +226,14 @@ __device__ void load_bonds(const WalkerDesc &w, Lds &L, int plan_words) {
 template <typename P>
 __device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc &bs, P X, int m, int c,
                                               bool inverse) {
+  using E = typename Elem<P>::T;
   const int b0 = w.col_start[c], nb = w.col_start[c + 1] - b0;
   const int tot = nb * m;
   // four (bond, column) updates per thread per round: all loads first, then
   // all stores (the bonds of one colour are disjoint, so nothing aliases)
   for (int t0 = TID; t0 < tot; t0 += 4 * kThreads) {
     size_t ii[4], jj[4];
-    double xi[4], xj[4], d[4], o[4];
+    E xi[4], xj[4], d[4], o[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int t = t0 + u * kThreads;
@@ -233,8 +242,10 @@ __device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc
       if (t < tot) {
         const int bb = m == 1 ? t : t / m, a = t - bb * m;
         int i, j;
-        bond_get(w, bs, b0 + bb, i, j, d[u], o[u]);
-        if (inverse) o[u] = -o[u];
+        double dd, oo;
+        bond_get(w, bs, b0 + bb, i, j, dd, oo);
+        d[u] = (E)dd;
+        o[u] = (E)(inverse ? -oo : oo);
         ii[u] = (size_t)i * m + a;
         jj[u] = (size_t)j * m + a;
         xi[u] = X[ii[u]];
@@ -253,12 +264,14 @@ __device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc
 
 template <typename P>
 __device__ __forceinline__ void diag_t(const WalkerDesc &w, P X, int m, int l, int sp, bool inverse) {
+  using E = typename Elem<P>::T;
   const int8_t *s = w.s + (size_t)(l - 1) * w.N;
   for (int i = TID; i < w.N; i += kThreads) {
     const int ss = sp == 0 ? s[i] : -s[i];
     double f = (ss > 0 ? w.elam : w.emlam) * w.eps_fac[i];
     if (inverse) f = 1.0 / f;
-    for (int a = 0; a < m; ++a) X[(size_t)i * m + a] *= f;
+    const E fe = (E)f;
+    for (int a = 0; a < m; ++a) X[(size_t)i * m + a] *= fe;
   }
   PassSync<P>::run();
 }
@@ -267,35 +280,41 @@ __device__ __forceinline__ bool in_lds(const void *p) {
   return __builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)p);
 }
 
-__device__ void colour_pass(const WalkerDesc &w, const Lds &L, double *X, int m, int c, bool inverse) {
+template <typename F>
+__device__ void colour_pass(const WalkerDesc &w, const Lds &L, F *X, int m, int c, bool inverse) {
   const BondSrc bs = bond_src(L, w);
   if (in_lds(X)) colour_pass_t(w, bs, as_lds(X), m, c, inverse);
   else colour_pass_t(w, bs, X, m, c, inverse);
 }
 // X <- E_K X : colour C-1 acts first
-__device__ void apply_ek(const WalkerDesc &w, const Lds &L, double *X, int m) {
+template <typename F>
+__device__ void apply_ek(const WalkerDesc &w, const Lds &L, F *X, int m) {
   for (int c = w.ncol - 1; c >= 0; --c) colour_pass(w, L, X, m, c, false);
 }
 // X <- E_K^T X : colour 0 acts first
-__device__ void apply_ekT(const WalkerDesc &w, const Lds &L, double *X, int m) {
+template <typename F>
+__device__ void apply_ekT(const WalkerDesc &w, const Lds &L, F *X, int m) {
   for (int c = 0; c < w.ncol; ++c) colour_pass(w, L, X, m, c, false);
 }
 // X <- D_l^{+-1} X for spin sp (l = 1..L)
-__device__ void apply_diag(const WalkerDesc &w, double *X, int m, int l, int sp, bool inverse) {
+template <typename F>
+__device__ void apply_diag(const WalkerDesc &w, F *X, int m, int l, int sp, bool inverse) {
   if (in_lds(X)) diag_t(w, as_lds(X), m, l, sp, inverse);
   else diag_t(w, X, m, l, sp, inverse);
 }
 
-__device__ void fill_P(const WalkerDesc &w, int sp, double *X) {
+template <typename F>
+__device__ void fill_P(const WalkerDesc &w, int sp, F *X) {
   const int m = w.ne[sp], tot = w.N * m;
-  for (int t = TID; t < tot; t += kThreads) X[t] = 0.0;
+  for (int t = TID; t < tot; t += kThreads) X[t] = (F)0;
   SYNC();
-  for (int a = TID; a < m; a += kThreads) X[(size_t)w.occ[sp][a] * m + a] = 1.0;
+  for (int a = TID; a < m; a += kThreads) X[(size_t)w.occ[sp][a] * m + a] = (F)1;
   SYNC();
 }
 
-__device__ void copy_global(double *dst, const double *src, size_t n) {
-  for (size_t t = TID; t < n; t += kThreads) dst[t] = src[t];
+template <typename D, typename S>
+__device__ void copy_global(D *dst, const S *src, size_t n) {
+  for (size_t t = TID; t < n; t += kThreads) dst[t] = (D)src[t];
   SYNC();
 }
 
@@ -310,15 +329,15 @@ __device__ __forceinline__ double gram_rows(PX X, int mx, int pa, PY Y, int my, 
   if (!sub) {
 #pragma unroll 2
     for (; i + 3 * G < N; i += 4 * G) {
-      a0 += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
-      a1 += X[(size_t)(i + G) * mx + pa] * Y[(size_t)(i + G) * my + qb];
-      a2 += X[(size_t)(i + 2 * G) * mx + pa] * Y[(size_t)(i + 2 * G) * my + qb];
-      a3 += X[(size_t)(i + 3 * G) * mx + pa] * Y[(size_t)(i + 3 * G) * my + qb];
+      a0 += (double)X[(size_t)i * mx + pa] * (double)Y[(size_t)i * my + qb];
+      a1 += (double)X[(size_t)(i + G) * mx + pa] * (double)Y[(size_t)(i + G) * my + qb];
+      a2 += (double)X[(size_t)(i + 2 * G) * mx + pa] * (double)Y[(size_t)(i + 2 * G) * my + qb];
+      a3 += (double)X[(size_t)(i + 3 * G) * mx + pa] * (double)Y[(size_t)(i + 3 * G) * my + qb];
     }
-    for (; i < N; i += G) a0 += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+    for (; i < N; i += G) a0 += (double)X[(size_t)i * mx + pa] * (double)Y[(size_t)i * my + qb];
   } else {
     for (; i < N; i += G)
-      if (sub[i] == sa) a0 += X[(size_t)i * mx + pa] * Y[(size_t)i * my + qb];
+      if (sub[i] == sa) a0 += (double)X[(size_t)i * mx + pa] * (double)Y[(size_t)i * my + qb];
   }
   return (a0 + a1) + (a2 + a3);
 }
@@ -352,8 +371,10 @@ __device__ void gram_t(PX X, int mx, PY Y, int my, int N, double *out, double *r
   }
 }
 
-// out[p][q] = sum_i X[i][p] Y[i][q] over rows i (optionally only sub[i] == a)
-__device__ void gram(const double *X, int mx, const double *Y, int my, int N, double *out,
+// out[p][q] = sum_i X[i][p] Y[i][q] over rows i (optionally only sub[i] == a),
+// accumulated in FP64 for FP32 or FP64 storage
+template <typename TX, typename TY>
+__device__ void gram(const TX *X, int mx, const TY *Y, int my, int N, double *out,
                      double *red, const int *sub = nullptr, int sa = 0) {
   if (mx * my == 0) { SYNC(); return; }
   const bool lx = in_lds(X), ly = in_lds(Y);
@@ -401,13 +422,14 @@ __device__ void tri_inverse(const double *R, int m, double *Ri) {
 }
 
 // out = in * Ri (Ri upper triangular), written to out and out2 (if set)
-__device__ void right_tri_mul(const double *in, double *out, double *out2, int N, int m, const double *Ri) {
+template <typename TI>
+__device__ void right_tri_mul(const TI *in, double *out, double *out2, int N, int m, const double *Ri) {
   const int tot = N * m;
   for (int t = TID; t < tot; t += kThreads) {
     const int i = t / m, c = t - (t / m) * m;
-    const double *row = in + (size_t)i * m;
+    const TI *row = in + (size_t)i * m;
     double s = 0.0;
-    for (int a = 0; a <= c; ++a) s += row[a] * Ri[a * m + c];
+    for (int a = 0; a <= c; ++a) s += (double)row[a] * Ri[a * m + c];
     out[t] = s;
     if (out2) out2[t] = s;
   }
@@ -420,7 +442,10 @@ __device__ void right_tri_mul(const double *in, double *out, double *out2, int N
 // triangular factor R = R_last ... R_1 goes to Vout (m x m, may be null).
 // tmp: N x m scratch distinct from Phi, q1, q2.  Vacc: m x m global scratch.
 // Returns sum_j log R_jj.
-__device__ double cholqr(const double *Phi, double *tmp, double *q1, double *q2, double *Vout,
+// Phi and q2 are FP64 or FP32 storage; the Gram matrices, factors and tmp,
+// q1 are FP64.
+template <typename F>
+__device__ double cholqr(const F *Phi, double *tmp, double *q1, F *q2, double *Vout,
                          double *Vacc, int N, int m, Lds &L, Scalars *sc) {
   if (m == 0) { SYNC(); return 0.0; }
   bool shifted = false;
@@ -473,7 +498,7 @@ __device__ double cholqr(const double *Phi, double *tmp, double *q1, double *q2,
   for (int t = TID; t < tot; t += kThreads) {
     const double v = qf[t];
     if (passes != 2) q1[t] = v;
-    if (q2) q2[t] = v;
+    if (q2) q2[t] = (F)v;
   }
   if (Vout)
     for (int t = TID; t < m * m; t += kThreads) Vout[t] = Vacc[t];
@@ -629,9 +654,9 @@ __device__ __forceinline__ double div_nr(double d, double r) {
 // Accepted flips of a chunk are returned as a bit mask (bit r = row r of the
 // chunk); the field flip and the row scaling Phi_R[i,:] *= 1 + Delta are
 // applied by flush_chunk, since no later site of the slice reads them.
-template <int T>
+template <int T, typename PE>
 __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], const double *xsb_g, int mm,
-                                    const double *prow_g, int ldp, const double *usb_g, const double *dsb_g, int cnt,
+                                    const PE *prow_g, int ldp, const double *usb_g, const double *dsb_g, int cnt,
                                     int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
   const int m = w.ne[sp];
@@ -640,7 +665,7 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
   const lds_f64 *dsb = as_lds(dsb_g) + sp * S;
   // right-row columns outside 0..m-1 are read from column 0: the matching
   // rows and columns of the register inverse are zero, so they add nothing
-  const lds_f64 *prow[2 * T];
+  decltype(as_lds(prow_g)) prow[2 * T];
 #pragma unroll
   for (int i = 0; i < 2 * T; ++i) {
     const int a = ar * 2 * T + i;
@@ -653,7 +678,7 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
 #pragma unroll
     for (int j = 0; j < T; ++j) R.x[j] = xsp[r * mm + j];
 #pragma unroll
-    for (int i = 0; i < 2 * T; ++i) R.p[i] = prow[i][r * ldp];
+    for (int i = 0; i < 2 * T; ++i) R.p[i] = (double)prow[i][r * ldp];
     R.d = dsb[r];
     R.u = usb[r];
   };
@@ -713,7 +738,8 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
 
 // LDS version for 32 < Ne <= 64: lane h of a half owns rows/columns h, h+32
 // of its spin's inverse, which stays in LDS (Ms0 / Ms1).
-__device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, int mm, const double *prow,
+template <typename PE>
+__device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, int mm, const PE *prow,
                                     int ldp, const double *usb, const int8_t *fsb, int cnt, int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31;
   const int m = w.ne[sp];
@@ -723,7 +749,7 @@ __device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *x
   unsigned mask = 0;
   for (int r = 0; r < cnt; ++r) {
     const double *xrow = xsp + r * mm;
-    const double *pr = prow + r * ldp;
+    const PE *pr = prow + r * ldp;
     const int sv = fsb[r];
     const int ss = sp == 0 ? sv : -sv;
     const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
@@ -776,20 +802,21 @@ __device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *x
 // Stage chunk c (rows i0 .. i0+cnt-1) of slice l into buffer bufi: left rows
 // (Phi_L'^T = E_K^T Y_l, stored by the left-stack build), right rows when
 // streamed, fields and the flip uniforms.  Threads t0.. of the caller.
+template <typename F>
 __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, int i0, int bufi,
-                            double *const phi[2], bool resident, int mm, int t0, int nt) {
+                            F *const phi[2], bool resident, int mm, int t0, int nt) {
   if (TID < t0 || TID >= t0 + nt) return;
   const int S = L.S, N = w.N;
   const int cnt = min(S, N - i0);
   for (int sp = 0; sp < 2; ++sp) {
     const int m = w.ne[sp];
-    const double *lx = w.LX[sp] + (size_t)(l - 1) * N * m;
+    const F *lx = reinterpret_cast<const F *>(w.LX[sp]) + (size_t)(l - 1) * N * m;
     double *xd = L.xs + (size_t)(bufi * 2 + sp) * S * mm;
     double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
     for (int e = TID - t0; e < cnt * mm; e += nt) {
       const int r = e / mm, a = e - (e / mm) * mm;
-      xd[e] = a < m ? lx[(size_t)(i0 + r) * m + a] : 0.0;
-      if (!resident && a < m) pd[e] = phi[sp][(size_t)(i0 + r) * m + a];
+      xd[e] = a < m ? (double)lx[(size_t)(i0 + r) * m + a] : 0.0;
+      if (!resident && a < m) pd[e] = (double)phi[sp][(size_t)(i0 + r) * m + a];
     }
   }
   const int8_t *srow = w.s + (size_t)(l - 1) * N;
@@ -807,7 +834,8 @@ __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, 
 // on their way back to device memory).  The streamed loop walks the staging
 // buffer in the order stage_chunk fills it, so the same thread reads an
 // element before it is restaged.
-__device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi, double *const phi[2],
+template <typename F>
+__device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi, F *const phi[2],
                             bool resident, int mm, int t0, int nt) {
   if (TID < t0 || TID >= t0 + nt) return;
   const int S = L.S, N = w.N;
@@ -825,7 +853,7 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
       if (mask != 0u)
         for (int e = TID - t0; e < cnt * m; e += nt) {
           const int r = e / m, a = e - r * m;
-          if ((mask >> r) & 1u) phi[sp][(size_t)(i0 + r) * m + a] *= factor(r);
+          if ((mask >> r) & 1u) phi[sp][(size_t)(i0 + r) * m + a] *= (F)factor(r);
         }
     } else {
       const double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
@@ -834,7 +862,7 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
         if (a < m) {
           double v = pd[e];
           if ((mask >> r) & 1u) v *= factor(r);
-          phi[sp][(size_t)(i0 + r) * m + a] = v;
+          phi[sp][(size_t)(i0 + r) * m + a] = (F)v;
         }
       }
     }
@@ -849,8 +877,8 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
 // All slices of block k with the inverse held by wave 0.  On entry D_{l0} has
 // been applied and Ms0/Ms1 hold the fresh inverse at the flip point of l0;
 // on exit Ms0/Ms1 hold the updated inverse and phi = B_k ... applied.
-template <int T>
-__device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, double *const phi[2],
+template <int T, typename F>
+__device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2],
                               bool resident, int mm, ChainAcc &acc) {
   constexpr int TT = T > 0 ? T : 1;
   const int N = w.N, S = L.S;
@@ -882,20 +910,23 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
         const int cnt = min(S, N - i0);
         if (TID < 64) {
           const double *xsb = L.xs + (size_t)bufi * 2 * S * mm;
-          double *prow;
-          int ldp;
-          if (resident) {
-            prow = phi[sp] + (size_t)i0 * w.ne[sp];
-            ldp = w.ne[sp];
-          } else {
-            prow = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
-            ldp = mm;
-          }
+          const double *us = L.us + bufi * S;
           unsigned mask;
-          if constexpr (T > 0)
-            mask = chain_chunk_reg<T>(w, M, xsb, mm, prow, ldp, L.us + bufi * S, L.dl + bufi * 2 * S, cnt, S, acc);
-          else
-            mask = chain_chunk_lds(w, L, xsb, mm, prow, ldp, L.us + bufi * S, L.fs + bufi * S, cnt, S, acc);
+          // right rows: the resident block (storage F) or the FP64 staging buffer
+          if (resident) {
+            const F *prow = phi[sp] + (size_t)i0 * w.ne[sp];
+            const int ldp = w.ne[sp];
+            if constexpr (T > 0)
+              mask = chain_chunk_reg<T>(w, M, xsb, mm, prow, ldp, us, L.dl + bufi * 2 * S, cnt, S, acc);
+            else
+              mask = chain_chunk_lds(w, L, xsb, mm, prow, ldp, us, L.fs + bufi * S, cnt, S, acc);
+          } else {
+            const double *prow = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
+            if constexpr (T > 0)
+              mask = chain_chunk_reg<T>(w, M, xsb, mm, prow, mm, us, L.dl + bufi * 2 * S, cnt, S, acc);
+            else
+              mask = chain_chunk_lds(w, L, xsb, mm, prow, mm, us, L.fs + bufi * S, cnt, S, acc);
+          }
           if (TID == 0) L.iscal[8 + bufi] = (int)mask;
         } else {
           if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
@@ -1184,6 +1215,9 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *__r
 // Y <- E_K^T Y, store X'_l = Y (the left state at the flip point of slice l,
 // (Phi_L(l) E_K)^T), Y <- D_l Y; at every block boundary a thin QR, LS[k-1] = Q.
 // LS[n] = P.  Y stays in LDS when it fits.
+// F: storage of the propagated block and of the stored left states (FP64, or
+// FP32 for mixed-precision walkers); the QR and the stack LS stay FP64.
+template <typename F>
 __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   Lds L = carve(pl);
@@ -1192,14 +1226,15 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__res
   {
     const int sp = blockIdx.x & 1;
     const int m = w.ne[sp];
-    double *Y = L.phi ? L.phi : w.X[sp];
+    F *Y = L.phi ? reinterpret_cast<F *>(L.phi) : reinterpret_cast<F *>(w.X[sp]);
+    F *LX = reinterpret_cast<F *>(w.LX[sp]);
     fill_P(w, sp, Y);
     copy_global(w.LS[sp] + (size_t)w.nblk * N * m, Y, (size_t)N * m);
     for (int k = w.nblk; k >= 1; --k) {
       const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
       for (int l = l1; l >= l0; --l) {
         apply_ekT(w, L, Y, m);
-        copy_global(w.LX[sp] + (size_t)(l - 1) * N * m, Y, (size_t)N * m);
+        copy_global(LX + (size_t)(l - 1) * N * m, Y, (size_t)N * m);
         apply_diag(w, Y, m, l, sp, false);
       }
       double *Q = w.LS[sp] + (size_t)(k - 1) * N * m;
@@ -1211,7 +1246,10 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__res
 // Forward pass over all slices with the HS-field flips, stabilisation at
 // block ends (push (Q_k, V_k)), wrap check and measurements at interior
 // boundaries, and the fresh weight and inverse at tau = beta.
-template <int TSEL>
+// F: storage of the propagated Slater blocks and of the stored left states
+// (FP64, or FP32 for mixed-precision walkers).  Ratios, inverses, QR and
+// weights are FP64 in both.
+template <int TSEL, typename F>
 __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restrict__ descs, LdsPlan pl, int want_aw) {
   const WalkerDesc &w = descs[blockIdx.x];
   Lds L = carve(pl);
@@ -1220,7 +1258,8 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
   const int N = w.N, n = w.nblk;
   const bool resident = L.phi != nullptr;
   const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
-  double *const phi[2] = {resident ? L.phi : w.PhiR[0], resident ? L.phi + (size_t)N * w.ne[0] : w.PhiR[1]};
+  F *const phi[2] = {resident ? reinterpret_cast<F *>(L.phi) : reinterpret_cast<F *>(w.PhiR[0]),
+                     resident ? reinterpret_cast<F *>(L.phi) + (size_t)N * w.ne[0] : reinterpret_cast<F *>(w.PhiR[1])};
   if (TID == 0) {
     Scalars *sc = w.sc;
     sc->logw += sc->fock_logw[0] + sc->fock_logw[1];
@@ -1237,13 +1276,13 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
     for (int sp = 0; sp < 2; ++sp) {
       const int m = w.ne[sp];
       apply_diag(w, phi[sp], m, l0, sp, false);
-      gram(w.LX[sp] + (size_t)(l0 - 1) * N * m, m, phi[sp], m, N, L.A, L.red);
+      gram(reinterpret_cast<const F *>(w.LX[sp]) + (size_t)(l0 - 1) * N * m, m, phi[sp], m, N, L.A, L.red);
       double la;
       int sg;
       if (m > 0 && !gj_inverse(L.A, sp ? L.Ms1 : L.Ms0, m, L, &la, &sg))
         if (TID == 0) w.sc->status |= 4;
     }
-    forward_block<TSEL>(w, k, sweep, L, phi, resident, mm, acc);
+    forward_block<TSEL, F>(w, k, sweep, L, phi, resident, mm, acc);
     // block end: diagonal of A from the updated inverse, kept for the wrap check
     if (k < n && want_aw)
       for (int sp = 0; sp < 2; ++sp) {
@@ -1404,10 +1443,11 @@ __device__ __forceinline__ int perm_col(int c, int k, int ne) {
 // loads issued before the call (the level's Q rows) stay in flight.
 constexpr int kFq = 4;   // sites per thread on the fast path (N <= 1024)
 constexpr int kFne = 8;  // Q columns cached in registers (Ne <= 8)
-__device__ __forceinline__ void fock_propagate(const WalkerDesc &w, int sp, double *fw, int l0, int l1,
+template <typename F>
+__device__ __forceinline__ void fock_propagate(const WalkerDesc &w, int sp, F *fw, int l0, int l1,
                                                const double (&eps)[kFq], const Lds &L) {
   const int N = w.N;
-  lds_f64 *v = as_lds(fw);
+  auto v = as_lds(fw);
   int fc[kFq], fn[kFq];
   auto fields = [&](int l, int (&f)[kFq]) {
     const int8_t *srow = w.s + (size_t)(l - 1) * N;
@@ -1424,7 +1464,7 @@ __device__ __forceinline__ void fock_propagate(const WalkerDesc &w, int sp, doub
     for (int q = 0; q < kFq; ++q) {
       const int i = TID + q * kThreads;
       const int ss = sp == 0 ? fc[q] : -fc[q];
-      if (i < N) v[i] *= (ss > 0 ? w.elam : w.emlam) * eps[q];
+      if (i < N) v[i] *= (F)((ss > 0 ? w.elam : w.emlam) * eps[q]);
     }
     lds_sync();
     apply_ek(w, L, fw, 1);
@@ -1433,9 +1473,12 @@ __device__ __forceinline__ void fock_propagate(const WalkerDesc &w, int sp, doub
   }
 }
 
-// returns accepted (uniform); *log_abs_r / *sign_r in scal
+// returns accepted (uniform); *log_abs_r / *sign_r in scal.  F: storage of
+// the propagated column (FP32 for mixed-precision walkers); projections,
+// norms, the stored columns q_i and every ratio are FP64.
+template <typename F>
 __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc, bool commit,
-                          Lds &L, double *fw, double *ratio_out) {
+                          Lds &L, F *fw, double *ratio_out) {
   const int N = w.N, ne = w.ne[sp], m = ne - 1, n = w.nblk, mm = w.mmax;
   // per-spin Fock scratch
   double *const fq = w.fq + (size_t)sp * n * N;
@@ -1538,7 +1581,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
   const double sign_rem = (mlast < 0.0 ? -1.0 : 1.0) * L.scal[21];
   // ---- addition ----
   if (L.scal[22] == 0.0) {
-    for (int i = TID; i < N; i += kThreads) fw[i] = (i == j) ? 1.0 : 0.0;
+    for (int i = TID; i < N; i += kThreads) fw[i] = (F)((i == j) ? 1 : 0);
     SYNC();
     const bool fast = in_lds(fw) && N <= kFq * kThreads;
     const bool qcache = fast && ne <= kFne;
@@ -1581,7 +1624,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
 #pragma unroll
           for (int q = 0; q < kFq; ++q) {
             const int i = TID + q * kThreads;
-            const double f = i < N ? fw[i] : 0.0;
+            const double f = i < N ? (double)fw[i] : 0.0;
 #pragma unroll
             for (int a = 0; a < kFne; ++a) yp[a] += qr[q][a] * f;
           }
@@ -1636,7 +1679,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         SYNC();
       }
       double nrm = 0.0;
-      for (int i = TID; i < N; i += kThreads) nrm += fw[i] * fw[i];
+      for (int i = TID; i < N; i += kThreads) nrm += (double)fw[i] * (double)fw[i];
       nrm = sqrt(wg_sum(nrm, L.red));
       if (!(nrm > 1e-300)) {
         if (TID == 0) L.scal[22] = 1.0;
@@ -1645,9 +1688,9 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       }
       double *q = fq + (size_t)lvl * N;
       for (int i = TID; i < N; i += kThreads) {
-        const double v = fw[i] / nrm;
+        const double v = (double)fw[i] / nrm;
         q[i] = v;
-        fw[i] = v;
+        fw[i] = (F)v;
       }
       if (TID == 0) {
         for (int a = 0; a < m; ++a) fv[(size_t)lvl * mm + a] = vsum[a];
@@ -1785,12 +1828,16 @@ __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
 
 // One workgroup per (walker, spin): the two species have separate stacks,
 // inverses and occupations, so their swap sequences are independent.
+template <typename F>
 __global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   const int sp = blockIdx.x & 1;
   Lds L = carve(pl);
   load_bonds(w, L, pl.bond_words);
-  double *fw = (L.phi && pl.phi_elems >= w.N) ? L.phi : w.fw + (size_t)sp * w.N;
+  // column storage: LDS when the plan holds N entries of F, else device memory
+  F *fw = (L.phi && (size_t)pl.phi_elems * sizeof(double) >= (size_t)w.N * sizeof(F))
+              ? reinterpret_cast<F *>(L.phi)
+              : reinterpret_cast<F *>(w.fw + (size_t)sp * w.N);
   const uint32_t sweep = (uint32_t)w.sc->sweep;
   const int ne = w.ne[sp];
   if ((w.flags & 1) || ne == 0 || ne == w.N) return;
@@ -1819,7 +1866,7 @@ __device__ void right_state(const WalkerDesc &w, int sp, int b, Lds &L) {
   for (int l = 1; l <= b; ++l) {
     apply_diag(w, Phi, m, l, sp, false);
     apply_ek(w, L, Phi, m);
-    if (l % w.nstab == 0 || l == b) cholqr(Phi, w.T[sp], Phi, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
+    if (l % w.nstab == 0 || l == b) cholqr<double>(Phi, w.T[sp], Phi, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
   }
 }
 // stabilised left state (P^T B_L ... B_{b+1})^T in X
@@ -1831,7 +1878,7 @@ __device__ void left_state(const WalkerDesc &w, int sp, int b, Lds &L) {
   for (int l = w.L; l > b; --l) {
     apply_ekT(w, L, Y, m);
     apply_diag(w, Y, m, l, sp, false);
-    if (++cnt % w.nstab == 0 || l == b + 1) cholqr(Y, w.T[sp], Y, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
+    if (++cnt % w.nstab == 0 || l == b + 1) cholqr<double>(Y, w.T[sp], Y, nullptr, nullptr, w.fVp, w.N, m, L, w.sc);
   }
 }
 
@@ -1929,19 +1976,29 @@ hipError_t launch_fresh_weight(const WalkerDesc *d, int n, LdsPlan p, int set_tr
   hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), b, st, d, p, set_tracked);
   return hipGetLastError();
 }
-hipError_t launch_left_stack(const WalkerDesc *d, int n, LdsPlan p, hipStream_t st) {
+hipError_t launch_left_stack(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStream_t st) {
   p = clamp_plan(p);
   const size_t b = lds_bytes(p);
-  lds_attr(k_left_stack, b);
-  hipLaunchKernelGGL(k_left_stack, dim3(2 * n), dim3(kThreads), b, st, d, p);
+  if (mixed) {
+    lds_attr(k_left_stack<float>, b);
+    hipLaunchKernelGGL(k_left_stack<float>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+  } else {
+    lds_attr(k_left_stack<double>, b);
+    hipLaunchKernelGGL(k_left_stack<double>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+  }
   return hipGetLastError();
 }
 // register tile of the flip chain chosen by the largest Ne of the launch
 template <int TSEL>
-static hipError_t launch_forward_t(const WalkerDesc *d, int n, LdsPlan p, int want_aw, hipStream_t st) {
+static hipError_t launch_forward_t(const WalkerDesc *d, int n, LdsPlan p, int want_aw, int mixed, hipStream_t st) {
   const size_t b = lds_bytes(p);
-  lds_attr(k_forward<TSEL>, b);
-  hipLaunchKernelGGL(k_forward<TSEL>, dim3(n), dim3(kThreads), b, st, d, p, want_aw);
+  if (mixed) {
+    lds_attr(k_forward<TSEL, float>, b);
+    hipLaunchKernelGGL((k_forward<TSEL, float>), dim3(n), dim3(kThreads), b, st, d, p, want_aw);
+  } else {
+    lds_attr(k_forward<TSEL, double>, b);
+    hipLaunchKernelGGL((k_forward<TSEL, double>), dim3(n), dim3(kThreads), b, st, d, p, want_aw);
+  }
   return hipGetLastError();
 }
 hipError_t launch_measure(const WalkerDesc *d, int n, int slots, LdsPlan p, hipStream_t st) {
@@ -1954,18 +2011,23 @@ hipError_t launch_measure(const WalkerDesc *d, int n, int slots, LdsPlan p, hipS
   hipLaunchKernelGGL(k_measure_sum, dim3(n), dim3(kThreads), 0, st, d);
   return hipGetLastError();
 }
-hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int do_measure, hipStream_t st) {
+hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int do_measure, int mixed, hipStream_t st) {
   p = clamp_plan(p);
-  if (p.mm <= 8) return launch_forward_t<1>(d, n, p, do_measure, st);
-  if (p.mm <= 16) return launch_forward_t<2>(d, n, p, do_measure, st);
-  if (p.mm <= 32) return launch_forward_t<4>(d, n, p, do_measure, st);
-  return launch_forward_t<0>(d, n, p, do_measure, st);
+  if (p.mm <= 8) return launch_forward_t<1>(d, n, p, do_measure, mixed, st);
+  if (p.mm <= 16) return launch_forward_t<2>(d, n, p, do_measure, mixed, st);
+  if (p.mm <= 32) return launch_forward_t<4>(d, n, p, do_measure, mixed, st);
+  return launch_forward_t<0>(d, n, p, do_measure, mixed, st);
 }
-hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, hipStream_t st) {
+hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStream_t st) {
   p = clamp_plan(p);
   const size_t b = lds_bytes(p);
-  lds_attr(k_fock, b);
-  hipLaunchKernelGGL(k_fock, dim3(2 * n), dim3(kThreads), b, st, d, p);
+  if (mixed) {
+    lds_attr(k_fock<float>, b);
+    hipLaunchKernelGGL(k_fock<float>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+  } else {
+    lds_attr(k_fock<double>, b);
+    hipLaunchKernelGGL(k_fock<double>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+  }
   return hipGetLastError();
 }
 hipError_t launch_green(const WalkerDesc *d, int mm, int b, int sp, double *G, hipStream_t st) {

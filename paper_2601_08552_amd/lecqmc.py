@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblecqmc.so")
 
 OK, EINVAL, ENOMEM, EUNSTABLE, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 FP64 = 0
+MIXED = 1
 NO_FOCK = 1
 NO_FLIPS = 2
 MAX_NE = 64

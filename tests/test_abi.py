@@ -36,6 +36,16 @@ def test_footprint_plan_scales_with_stacks():
     assert stacks < fb < stacks * 1.3
 
 
+def test_mixed_footprint_halves_the_stored_left_states():
+    """Mixed precision stores the per-slice left states in FP32: the plan
+    shrinks by L_tau * N * Ne * 4 bytes per spin and nothing else."""
+    lat, par = W.config_dilute()
+    mix = W.config_dilute(precision=lecqmc.MIXED)[1]
+    fb, fm = lecqmc.footprint_bytes(lat, par), lecqmc.footprint_bytes(lat, mix)
+    saved = 2 * 320 * 1024 * 8 * 4
+    assert abs((fb - fm) - saved) <= 2 * 256
+
+
 @pytest.mark.parametrize("bad", [
     dict(dtau=0.35),          # beta / dtau not integral
     dict(n_stab=0),
