@@ -131,6 +131,19 @@ int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measure);
  * combined: each precision gets its own launch per phase. */
 int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure);
 
+/* A fixed batch of walkers of one context (uneven shapes and precisions
+ * allowed): their descriptors are uploaded once, so lecqmc_batch_sweep only
+ * launches kernels on the context's stream -- no allocation, copy,
+ * synchronisation or event -- and a call may be recorded into a HIP graph
+ * by stream capture and replayed (every replay advances the walkers by the
+ * recorded sweeps; the sweep counters live on the device).  Phase timing
+ * (lecqmc_ctx_set_timing) does not see these sweeps.  A walker of a live
+ * batch cannot be destroyed (LECQMC_ESTATE); destroy the batch first. */
+typedef struct lecqmc_batch lecqmc_batch;
+int lecqmc_batch_create(lecqmc_walker *const *ws, int32_t n, lecqmc_batch **out);
+int lecqmc_batch_sweep(lecqmc_batch *b, int32_t n_sweeps, int32_t do_measure);
+int lecqmc_batch_destroy(lecqmc_batch *b);
+
 /* Fresh log|W| and sign from the current (eta, s) (right chain + QR, FP64
  * whatever the walker's precision). */
 int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);

@@ -70,6 +70,7 @@ struct lecqmc_walker {
   size_t bytes;
   double *d_green;
   int N, L, nblk, ne[2], mmax, nobs;
+  int batches;           // live lecqmc_batch objects that hold this walker
 };
 
 extern "C" const char *lecqmc_last_error(void) { return g_err; }
@@ -517,6 +518,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
 
 extern "C" int lecqmc_destroy_walker(lecqmc_walker *w) {
   if (!w) return 0;
+  if (w->batches > 0) return fail(LECQMC_ESTATE, "walker still belongs to %d batch(es)", w->batches);
   (void)hipSetDevice(w->ctx->device);
   (void)hipStreamSynchronize(w->ctx->stream);
   if (w->d_green) (void)hipFree(w->d_green);
@@ -592,6 +594,84 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
     HIPCHK(timed(c, 2, [&] { return each([&](const Group &g) {
       return launch_fock(g.d, g.n, g.cf.fock, g.cf.mixed, c->stream); }); }));
   }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// fixed batches: descriptors uploaded once, sweeps that only launch kernels
+// ---------------------------------------------------------------------------
+struct lecqmc_batch {
+  lecqmc_ctx *ctx;
+  std::vector<lecqmc_walker *> ws;
+  WalkerDesc *d;
+  int n, n64;
+  LaunchCfg cf64, cfmx;
+};
+
+extern "C" int lecqmc_batch_create(lecqmc_walker *const *ws, int32_t n, lecqmc_batch **out) {
+  if (!ws || n <= 0 || !out) return fail(LECQMC_EINVAL, "bad arguments");
+  lecqmc_ctx *c = ws[0] ? ws[0]->ctx : nullptr;
+  std::vector<lecqmc_walker *> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int t = 0; t < n; ++t) {
+      if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers of a batch must share one context");
+      if (ws[t]->h.mixed == pass) order.push_back(ws[t]);
+    }
+  for (int t = 0; t < n; ++t)
+    for (int u = t + 1; u < n; ++u)
+      if (order[t] == order[u]) return fail(LECQMC_EINVAL, "a walker appears twice in the batch");
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<WalkerDesc> hd(n);
+  int n64 = 0;
+  for (int t = 0; t < n; ++t) {
+    hd[t] = order[t]->h;
+    n64 += order[t]->h.mixed ? 0 : 1;
+  }
+  WalkerDesc *d = nullptr;
+  HIPCHK(hipMalloc(&d, sizeof(WalkerDesc) * n));
+  const hipError_t e = hipMemcpy(d, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return fail(LECQMC_EDEVICE, "upload: %s", hipGetErrorString(e));
+  }
+  lecqmc_batch *b = new lecqmc_batch();
+  b->ctx = c;
+  b->ws = order;
+  b->d = d;
+  b->n = n;
+  b->n64 = n64;
+  if (n64 > 0) b->cf64 = launch_cfg(order.data(), n64);
+  if (n > n64) b->cfmx = launch_cfg(order.data() + n64, n - n64);
+  for (lecqmc_walker *w : order) w->batches += 1;
+  *out = b;
+  return 0;
+}
+
+extern "C" int lecqmc_batch_sweep(lecqmc_batch *b, int32_t n_sweeps, int32_t do_measure) {
+  if (!b || n_sweeps < 0) return fail(LECQMC_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(b->ctx->device));
+  hipStream_t st = b->ctx->stream;
+  for (int t = 0; t < n_sweeps; ++t)
+    for (int g = 0; g < 2; ++g) {
+      const int gn = g == 0 ? b->n64 : b->n - b->n64;
+      if (gn == 0) continue;
+      const WalkerDesc *d = g == 0 ? b->d : b->d + b->n64;
+      const LaunchCfg &cf = g == 0 ? b->cf64 : b->cfmx;
+      HIPCHK(launch_left_stack(d, gn, cf.left, cf.mixed, st));
+      HIPCHK(launch_forward(d, gn, cf.fwd, do_measure, cf.mixed, st));
+      if (do_measure) HIPCHK(launch_measure(d, gn, cf.slots, cf.meas, st));
+      HIPCHK(launch_fock(d, gn, cf.fock, cf.mixed, st));
+    }
+  return 0;
+}
+
+extern "C" int lecqmc_batch_destroy(lecqmc_batch *b) {
+  if (!b) return 0;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
+  (void)hipFree(b->d);
+  for (lecqmc_walker *w : b->ws) w->batches -= 1;
+  delete b;
   return 0;
 }
 

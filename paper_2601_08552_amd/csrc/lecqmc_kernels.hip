@@ -1956,9 +1956,20 @@ __global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *__res
 static int clamp_mm(int mm) { return mm < 1 ? 1 : mm; }
 
 // allow dynamic LDS above the 64 KiB default
+// The dynamic-LDS limit of a kernel is raised once to the largest size asked
+// for; later launches (also those recorded into a graph) make no call.
 template <typename K>
 static void lds_attr(K kernel, size_t bytes) {
-  if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (bytes <= 65536) return;
+  static const void *keys[64];
+  static size_t done[64];
+  const void *k = (const void *)kernel;
+  int slot = -1;
+  for (int t = 0; t < 64; ++t)
+    if (keys[t] == k || keys[t] == nullptr) { slot = t; break; }
+  if (slot >= 0 && keys[slot] == k && done[slot] >= bytes) return;
+  (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (slot >= 0) { keys[slot] = k; done[slot] = bytes > done[slot] ? bytes : done[slot]; }
 }
 
 hipError_t launch_init(const WalkerDesc *d, int draw_fields, int draw_occ, hipStream_t st) {

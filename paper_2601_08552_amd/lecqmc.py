@@ -31,6 +31,7 @@ EXPORTED = [
     "lecqmc_sweep_batch", "lecqmc_log_weight", "lecqmc_tracked_weight", "lecqmc_obs_size",
     "lecqmc_measure", "lecqmc_reset_measure", "lecqmc_get_stats", "lecqmc_get_state",
     "lecqmc_set_state", "lecqmc_green", "lecqmc_flip_ratio", "lecqmc_swap_ratio", "lecqmc_last_error",
+    "lecqmc_batch_create", "lecqmc_batch_sweep", "lecqmc_batch_destroy",
 ]
 
 
@@ -63,12 +64,16 @@ class SweepStats(C.Structure):
 
 _lib = None
 _live_walkers: "weakref.WeakSet" = weakref.WeakSet()
+_live_batches: "weakref.WeakSet" = weakref.WeakSet()
 _live_contexts: "weakref.WeakSet" = weakref.WeakSet()
 
 
 @atexit.register
 def _release_all():
-    """Free device state while the HIP runtime is still up (walkers first)."""
+    """Free device state while the HIP runtime is still up (batches, then
+    walkers, then contexts)."""
+    for b in list(_live_batches):
+        b.close()
     for w in list(_live_walkers):
         w.close()
     for c in list(_live_contexts):
@@ -81,6 +86,14 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not built; run __graft_entry__.build()")
+        # One HIP runtime per process: torch ships its own libamdhip64 (soname
+        # libamdhip64.so.7, loaded by torch as libamdhip64.so).  Loading torch
+        # first lets the dynamic linker bind this library to that copy; the
+        # other order would map a second runtime that torch cannot share.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
@@ -107,6 +120,9 @@ def load():
             "lecqmc_flip_ratio": (C.c_int, [vp, i32, i32, C.POINTER(dbl)]),
             "lecqmc_swap_ratio": (C.c_int, [vp, i32, i32, i32, C.POINTER(dbl)]),
             "lecqmc_last_error": (C.c_char_p, []),
+            "lecqmc_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp)]),
+            "lecqmc_batch_sweep": (C.c_int, [vp, i32, i32]),
+            "lecqmc_batch_destroy": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -158,6 +174,7 @@ class Context:
         self.h = h
         self.device = device
         self._walkers = weakref.WeakSet()
+        self._batches = weakref.WeakSet()
         _live_contexts.add(self)
 
     def synchronize(self):
@@ -179,6 +196,8 @@ class Context:
     def close(self):
         """Destroy the context and every walker it still owns."""
         if getattr(self, "h", None):
+            for b in list(self._batches):
+                b.close()
             for w in list(self._walkers):
                 w.close()
             _check(load().lecqmc_ctx_destroy(self.h))
@@ -216,8 +235,8 @@ class Walker:
 
     def close(self):
         if getattr(self, "h", None):
-            load().lecqmc_destroy_walker(self.h)
-            self.h = None
+            if load().lecqmc_destroy_walker(self.h) == 0:
+                self.h = None
 
     def __del__(self):
         try:
@@ -287,3 +306,32 @@ class Walker:
 def sweep_batch(walkers, n_sweeps=1, measure=False):
     arr = (C.c_void_p * len(walkers))(*[w.h for w in walkers])
     _check(load().lecqmc_sweep_batch(arr, len(walkers), n_sweeps, 1 if measure else 0))
+
+
+class Batch:
+    """A fixed set of walkers whose sweeps only launch kernels on the
+    context's stream (so they may be captured into a HIP graph)."""
+
+    def __init__(self, walkers):
+        self.walkers = list(walkers)
+        arr = (C.c_void_p * len(self.walkers))(*[w.h for w in self.walkers])
+        h = C.c_void_p()
+        _check(load().lecqmc_batch_create(arr, len(self.walkers), C.byref(h)))
+        self.h = h
+        if self.walkers:
+            self.walkers[0].ctx._batches.add(self)
+        _live_batches.add(self)
+
+    def sweep(self, n_sweeps=1, measure=False):
+        _check(load().lecqmc_batch_sweep(self.h, n_sweeps, 1 if measure else 0))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lecqmc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
