@@ -69,6 +69,7 @@ struct Lds {
   double *bonds;  // compact bond tables (coef | bij | bci), or nullptr
   int S;          // sites per staged chunk
   bool bonds_ok;  // the walker's bond tables were copied into LDS
+  int *cs;        // colour offsets copied into LDS (iscal + 16), or nullptr
 };
 
 __host__ __device__ inline int chunk_size(int mm) { return mm <= 16 ? 32 : (mm <= 32 ? 16 : 4); }
@@ -110,6 +111,7 @@ __device__ Lds carve(const LdsPlan &pl) {
   L.iscal = reinterpret_cast<int *>(p);
   L.S = S;
   L.bonds_ok = false;
+  L.cs = nullptr;
   return L;
 }
 __device__ Lds carve(int mm, int phi_elems) {
@@ -180,11 +182,13 @@ struct BondSrc {
   const lds_f64 *coef;
   const lds_i32 *bij;
   const lds_u8 *bci;
+  const lds_i32 *cs;  // colour offsets in LDS, or nullptr
   bool lds;
 };
 __device__ __forceinline__ BondSrc bond_src(const Lds &L, const WalkerDesc &w) {
   BondSrc b;
   b.lds = L.bonds_ok;
+  b.cs = L.cs ? (const lds_i32 *)L.cs : nullptr;
   double *base = L.bonds ? L.bonds : L.red;
   b.coef = as_lds(base);
   b.bij = (const lds_i32 *)(as_lds(base) + 2 * kMaxCoef);
@@ -209,55 +213,69 @@ __device__ __forceinline__ void bond_get(const WalkerDesc &w, const BondSrc &bs,
 }
 
 // copy the compact bond tables of walker w into LDS (all threads)
+// copy the compact bond tables of walker w into LDS, and the colour offsets
+// (read at every colour pass) when there are at most 47 colours (all threads)
 __device__ void load_bonds(const WalkerDesc &w, Lds &L, int plan_words) {
+  if (w.ncol + 1 <= 48) {
+    for (int t = TID; t <= w.ncol; t += kThreads) L.iscal[16 + t] = w.col_start[t];
+    L.cs = L.iscal + 16;
+  }
   L.bonds_ok = L.bonds != nullptr && w.ncoef > 0 && w.bond_words <= plan_words;
-  if (!L.bonds_ok) return;
-  lds_f64 *coef = as_lds(L.bonds);
-  lds_i32 *bij = (lds_i32 *)(coef + 2 * kMaxCoef);
-  lds_u8 *bci = (lds_u8 *)(bij + w.nbonds);
-  for (int t = TID; t < 2 * w.ncoef; t += kThreads) coef[t] = w.coef[t];
-  for (int t = TID; t < w.nbonds; t += kThreads) {
-    bij[t] = w.bij[t];
-    bci[t] = w.bci[t];
+  if (L.bonds_ok) {
+    lds_f64 *coef = as_lds(L.bonds);
+    lds_i32 *bij = (lds_i32 *)(coef + 2 * kMaxCoef);
+    lds_u8 *bci = (lds_u8 *)(bij + w.nbonds);
+    for (int t = TID; t < 2 * w.ncoef; t += kThreads) coef[t] = w.coef[t];
+    for (int t = TID; t < w.nbonds; t += kThreads) {
+      bij[t] = w.bij[t];
+      bci[t] = w.bci[t];
+    }
   }
   SYNC();
+}
+__device__ __forceinline__ int colour_begin(const WalkerDesc &w, const BondSrc &bs, int c) {
+  return bs.cs ? bs.cs[c] : w.col_start[c];
 }
 
 template <typename P>
 __device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc &bs, P X, int m, int c,
                                               bool inverse) {
   using E = typename Elem<P>::T;
-  const int b0 = w.col_start[c], nb = w.col_start[c + 1] - b0;
-  const int tot = nb * m;
-  // four (bond, column) updates per thread per round: all loads first, then
-  // all stores (the bonds of one colour are disjoint, so nothing aliases)
-  for (int t0 = TID; t0 < tot; t0 += 4 * kThreads) {
-    size_t ii[4], jj[4];
-    E xi[4], xj[4], d[4], o[4];
+  const int b0 = colour_begin(w, bs, c), b1 = colour_begin(w, bs, c + 1);
+  // thread = (bond slot, column): column fastest, so neighbouring lanes touch
+  // neighbouring words of a row; one division per pass, 32-bit indices
+  const int per = m > 0 ? kThreads / m : 0;
+  const int col = m > 0 ? TID % m : 0, slot = m > 0 ? TID / m : kThreads;
+  if (slot < per) {
+    // four bonds per thread per round: all loads first, then all stores (the
+    // bonds of one colour are disjoint, so nothing aliases)
+    for (int bb = b0 + slot; bb < b1; bb += 4 * per) {
+      int ii[4], jj[4];
+      E xi[4], xj[4], d[4], o[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = t0 + u * kThreads;
-      ii[u] = jj[u] = 0;
-      xi[u] = xj[u] = d[u] = o[u] = 0.0;
-      if (t < tot) {
-        const int bb = m == 1 ? t : t / m, a = t - bb * m;
-        int i, j;
-        double dd, oo;
-        bond_get(w, bs, b0 + bb, i, j, dd, oo);
-        d[u] = (E)dd;
-        o[u] = (E)(inverse ? -oo : oo);
-        ii[u] = (size_t)i * m + a;
-        jj[u] = (size_t)j * m + a;
-        xi[u] = X[ii[u]];
-        xj[u] = X[jj[u]];
+      for (int u = 0; u < 4; ++u) {
+        const int b = bb + u * per;
+        ii[u] = jj[u] = 0;
+        xi[u] = xj[u] = d[u] = o[u] = (E)0;
+        if (b < b1) {
+          int i, j;
+          double dd, oo;
+          bond_get(w, bs, b, i, j, dd, oo);
+          d[u] = (E)dd;
+          o[u] = (E)(inverse ? -oo : oo);
+          ii[u] = i * m + col;
+          jj[u] = j * m + col;
+          xi[u] = X[ii[u]];
+          xj[u] = X[jj[u]];
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (bb + u * per < b1) {
+          X[ii[u]] = d[u] * xi[u] + o[u] * xj[u];
+          X[jj[u]] = o[u] * xi[u] + d[u] * xj[u];
+        }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (t0 + u * kThreads < tot) {
-        X[ii[u]] = d[u] * xi[u] + o[u] * xj[u];
-        X[jj[u]] = o[u] * xi[u] + d[u] * xj[u];
-      }
   }
   PassSync<P>::run();
 }
