@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--walkers", type=int, default=N_WALKERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default flip-chain shapes")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 256-walker uneven batch")
     ap.add_argument("--cpu-procs", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=10)
     args = ap.parse_args()
@@ -121,6 +123,9 @@ def main():
         for s in range(args.walkers):
             lat, par = W.config_dilute(seed=s + 1, walker_id=s, precision=precision)
             walkers.append(lecqmc.Walker(ctx, lat, par))
+        t_tune = time.perf_counter()
+        tuned = lecqmc.autotune(walkers) if not args.no_autotune else None
+        t_tune = time.perf_counter() - t_tune
         for _ in range(args.warmup):
             lecqmc.sweep_batch(walkers, 1)
         ctx.synchronize()
@@ -142,10 +147,55 @@ def main():
         lt, _ = walkers[0].tracked_weight()
         lf, _ = walkers[0].log_weight()
         res = dict(wall=wall, ms_phase=ms_phase, cnt=cnt, step_ms=step_ms, stats=walkers[0].stats(),
-                   logw_rel_err=abs(lt - lf) / max(1.0, abs(lf)), lat=lat, par=par)
+                   logw_rel_err=abs(lt - lf) / max(1.0, abs(lf)), lat=lat, par=par,
+                   shape={"tile": walkers[0].shape[0], "chunk": walkers[0].shape[1],
+                          "autotuned": tuned is not None, "tune_s": t_tune if tuned is not None else 0.0})
         for w in walkers:
             w.close()
         return res
+
+    def run_uneven():
+        """The batched uneven-walker workload: 256 chains of mixed lattice size,
+        Ne and beta, autotuned, one fixed batch, each sweep a HIP graph replay."""
+        cfg = W.config_batched(256)
+        gs = torch.cuda.Stream()
+        gctx = lecqmc.Context(0, stream=gs)
+        ws = [lecqmc.Walker(gctx, lat, par) for lat, par in cfg]
+        t_tune = time.perf_counter()
+        res = lecqmc.autotune(ws)
+        t_tune = time.perf_counter() - t_tune
+        batch = lecqmc.Batch(ws)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            batch.sweep(1)
+        torch.cuda.synchronize()
+        graph.replay()                                 # warm-up sweep
+        torch.cuda.synchronize()
+        k = max(1, min(args.steps, 3))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+        t0 = time.perf_counter()
+        with torch.cuda.stream(gs):
+            ev[0].record(gs)
+            for q in range(k):
+                graph.replay()
+                ev[q + 1].record(gs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        step_ms = [ev[q].elapsed_time(ev[q + 1]) for q in range(k)]
+        upd = sum(lat.n_sites * par.L_tau for lat, par in cfg) * k
+        fwd = sorted(r[2] for r in res)
+        out = {"value": upd / wall, "unit": "HS-field updates/s", "walkers": len(ws), "steps": k,
+               "ms_per_step": wall * 1e3 / k,
+               "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+               "updates_per_sweep": upd // k, "hbm_gib": gctx.bytes_in_use() / 2**30,
+               "autotune_s": t_tune, "shapes": {f"{t},{c}": sum(1 for r in res if r[:2] == (t, c))
+                                                 for (t, c) in sorted({r[:2] for r in res})},
+               "forward_ms_per_walker": {"min": fwd[0], "median": fwd[len(fwd) // 2], "max": fwd[-1]},
+               "config": "256 chains: L x L square, L in {16,24,32,48,64}, Ne per spin in [4,32], U in [2,6], "
+                         "beta in {8,16}, dtau=0.05, QR every 10 slices, FP64; sweeps replayed from a HIP graph"}
+        batch.close()
+        gctx.close()
+        return out
 
     r64 = run(lecqmc.FP64)
     rmx = None if args.no_mixed else run(lecqmc.MIXED)
@@ -178,6 +228,7 @@ def main():
                    "ne_per_spin": par.n_up},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "note": "per-walker sweep latency = batched step time (all walkers advance together)"},
+        "chain_shape": r64["shape"],
         "phase_ms_per_launch": {"left_stack": ms_phase[0] / max(cnt[0], 1), "forward": fwd_ms,
                                 "fock": ms_phase[2] / max(cnt[2], 1)},
         "accuracy": {"vs_oracle": "bit-identical Markov chain; log-weight, Green's function and ratios "
@@ -196,6 +247,7 @@ def main():
         out["mixed"] = {
             "value": updates / rmx["wall"], "unit": "HS-field updates/s", "ms_per_step": rmx["wall"] * 1e3 / args.steps,
             "dtype": "f32 propagation / f64 QR, inverses, ratios, weights",
+            "chain_shape": rmx["shape"],
             "latency_ms": {"p50": float(np.percentile(rmx["step_ms"], 50)),
                            "p99": float(np.percentile(rmx["step_ms"], 99))},
             "phase_ms_per_launch": {"left_stack": mp_[0] / max(mc_[0], 1), "forward": mp_[1] / max(mc_[1], 1),
@@ -205,6 +257,8 @@ def main():
                          "vs_oracle": "first sweep of the 32x32 workload: identical fields and log|W| within "
                                       "1e-5 relative; estimators within 1e-4 (mixed parity tests)"},
         }
+    if not args.no_uneven:
+        out["uneven_batch"] = run_uneven()
     if not args.no_cpu_baseline:
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(procs, args.cpu_sweeps)

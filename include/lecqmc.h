@@ -144,6 +144,33 @@ int lecqmc_batch_create(lecqmc_walker *const *ws, int32_t n, lecqmc_batch **out)
 int lecqmc_batch_sweep(lecqmc_batch *b, int32_t n_sweeps, int32_t do_measure);
 int lecqmc_batch_destroy(lecqmc_batch *b);
 
+/* Flip-chain shape of a walker.  tile = register tile T in {1, 2, 4}: the
+ * Ne x Ne inverse of each spin is held in registers of one wavefront, which
+ * needs Ne <= 8T; tile = 0: the inverse stays in LDS (any Ne).  chunk = sites
+ * staged per step of the chain: 4, 8, 16 or 32.  New walkers take a default
+ * by Ne, or the shape an earlier lecqmc_autotune chose in the same context
+ * for the same (n_sites, n_up, n_dn, precision).  Every shape samples the
+ * same chain: the tile changes only the rounding order of the ratio sums,
+ * the chunk changes nothing.  A walker's shape is its own: walkers of
+ * different shapes in one batch keep theirs.  set_shape returns
+ * LECQMC_EINVAL for a shape that is not valid for the walker's Ne and
+ * LECQMC_ESTATE while the walker belongs to a batch. */
+int lecqmc_get_shape(const lecqmc_walker *w, int32_t *tile, int32_t *chunk);
+int lecqmc_set_shape(lecqmc_walker *w, int32_t tile, int32_t chunk);
+/* Autotuner: runs one whole forward pass of the given walkers for every
+ * (tile, chunk) that is valid for them (walkers of one precision launched
+ * together), times each walker by the device wall clock inside the kernel,
+ * and restores every walker's fields and scalars after each candidate.  The
+ * walkers of one (n_sites, n_up, n_dn, precision) key then all get the shape
+ * with the least total time over them, and the context records it for that
+ * key.  The Markov chains are not advanced.  Outputs, arrays of n that may
+ * each be NULL: the chosen tile and chunk, and the walker's forward-pass
+ * milliseconds with them.  Synchronises the context's stream and allocates
+ * device memory for the saved state.  LECQMC_ESTATE if a walker belongs to
+ * a batch. */
+int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *tile_out, int32_t *chunk_out,
+                    double *fwd_ms_out);
+
 /* Fresh log|W| and sign from the current (eta, s) (right chain + QR, FP64
  * whatever the walker's precision). */
 int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lecqmc.h"
@@ -41,6 +43,9 @@ struct lecqmc_ctx {
   struct Rec { int phase; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  // autotuned flip-chain shapes by (N, Ne_up, Ne_dn, precision); new walkers
+  // of a tuned key start with its shape
+  std::map<std::tuple<int, int, int, int>, std::pair<int, int>> tuned;
 };
 
 static hipEvent_t take_event(lecqmc_ctx *c) {
@@ -75,22 +80,58 @@ struct lecqmc_walker {
 
 extern "C" const char *lecqmc_last_error(void) { return g_err; }
 
-// LDS plan per launch: a phase keeps its Slater blocks (then the compact bond
-// tables) in LDS when the largest walker of the launch fits next to the
-// fixed layout.
+// Flip-chain shape of a walker: the register tile T (the Ne x Ne inverse in
+// registers for Ne <= 8T, or T = 0: in LDS) and the sites per staged chunk.
+// Defaults by Ne, measured on the dilute workload; lecqmc_autotune replaces
+// them by timed choices.  Every shape computes the same chain; the tile
+// changes the order of the ratio's partial sums (rounding only), the chunk
+// changes nothing.
+static void shape_default(int mmax, int *tile, int *chunk) {
+  *tile = mmax <= 8 ? 1 : mmax <= 16 ? 2 : mmax <= 32 ? 4 : 0;
+  *chunk = mmax <= 16 ? 32 : mmax <= 32 ? 16 : 4;
+}
+static int shape_xld(int mmax, int tile) { return tile > 0 ? 8 * tile : mmax; }
+static bool shape_valid(int mmax, int tile, int chunk) {
+  if (!(tile == 0 || tile == 1 || tile == 2 || tile == 4)) return false;
+  if (tile > 0 && mmax > 8 * tile) return false;
+  if (!(chunk == 4 || chunk == 8 || chunk == 16 || chunk == 32)) return false;
+  // both staging buffers (streamed walker) must fit next to the fixed layout
+  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk};
+  return lds_bytes(p) <= kLdsLimit;
+}
+static void shape_apply(WalkerDesc &h, int tile, int chunk) {
+  h.tile = tile;
+  h.chunk = chunk;
+  h.xld = shape_xld(h.mmax, tile);
+}
+
+// LDS plan per launch: the fixed layout for the largest Ne and chunk of the
+// launch, then room for resident Slater blocks (then the compact bond
+// tables).  When the largest walker's blocks do not fit, the room is sized
+// for the largest that do; the others stream theirs.
 struct LaunchCfg {
   LdsPlan fwd, left, fock, meas;
   LdsPlan fresh;  // FP64 right chain of the fresh weight (all walkers)
   int slots;
   int mixed;      // FP32 storage in the sweep phases
+  int tile;       // chain shape shared by all walkers, -1 if they differ
 };
 
-static LdsPlan plan_for(int mm, long phi_need, int bond_need, bool staged_if_streamed) {
-  LdsPlan p{mm, 0, 0, 0};
-  p.phi_elems = (int)phi_need;
-  if (phi_need <= 0 || lds_bytes(p) > kLdsLimit) {
+static LdsPlan plan_for(LdsPlan p, const std::vector<long> &needs, int bond_need, bool staged_if_streamed) {
+  long mx = 0;
+  for (long v : needs) mx = std::max(mx, v);
+  p.phi_elems = (int)mx;
+  p.stage_ps = 0;
+  p.bond_words = 0;
+  if (mx <= 0 || lds_bytes(p) > kLdsLimit) {
     p.phi_elems = 0;
     p.stage_ps = staged_if_streamed ? 1 : 0;
+    const size_t base = lds_bytes(p);
+    const long cap = base < kLdsLimit ? (long)((kLdsLimit - base) / sizeof(double)) : 0;
+    long best = 0;
+    for (long v : needs)
+      if (v <= cap) best = std::max(best, v);
+    p.phi_elems = (int)best;
   }
   if (bond_need > 0) {
     p.bond_words = bond_need;
@@ -102,26 +143,30 @@ static LdsPlan plan_for(int mm, long phi_need, int bond_need, bool staged_if_str
 // Walkers of one launch share a precision (the sweep launchers group them).
 // Resident blocks are counted in doubles: FP32 storage needs half of them.
 static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
-  int mm = 1, bonds = 0, slots = 1;
-  long fwd = 0, left = 0, fock = 0, fresh = 0;
+  int mm = 1, bonds = 0, slots = 1, xs = 0, smax = 0, tile = n > 0 ? ws[0]->h.tile : 0;
+  std::vector<long> fwd, left, fock, fresh;
   bool compact = true;
   const int mixed = n > 0 ? ws[0]->h.mixed : 0;
-  auto in_doubles = [&](long entries) { return mixed ? (entries + 1) / 2 : entries; };
+  const int eb = mixed ? (int)sizeof(float) : (int)sizeof(double);
   for (int t = 0; t < n; ++t) {
     const lecqmc_walker *w = ws[t];
     mm = std::max(mm, w->mmax);
-    fwd = std::max(fwd, in_doubles((long)w->N * (w->ne[0] + w->ne[1])));
-    left = std::max(left, in_doubles((long)w->N * std::max(w->ne[0], w->ne[1])));
-    fock = std::max(fock, in_doubles((long)w->N));
-    fresh = std::max(fresh, (long)w->N * std::max(w->ne[0], w->ne[1]));
+    xs = std::max(xs, 4 * w->h.chunk * w->h.xld);
+    smax = std::max(smax, w->h.chunk);
+    fwd.push_back(phi_doubles((long)w->N * (w->ne[0] + w->ne[1]), eb));
+    left.push_back(phi_doubles((long)w->N * std::max(w->ne[0], w->ne[1]), eb));
+    fock.push_back(phi_doubles((long)w->N, eb));
+    fresh.push_back((long)w->N * std::max(w->ne[0], w->ne[1]));
     if (w->h.ncoef == 0) compact = false;
     bonds = std::max(bonds, w->h.bond_words);
     slots = std::max(slots, w->nblk - 1);
+    if (w->h.tile != tile) tile = -1;
   }
   if (!compact) bonds = 0;
-  return {plan_for(mm, fwd, bonds, true),  plan_for(mm, left, bonds, false), plan_for(mm, fock, bonds, false),
-          LdsPlan{mm, 0, 0, 0},            plan_for(mm, fresh, bonds, false), slots,
-          mixed};
+  const LdsPlan base{mm, 0, 0, 0, 0, 0}, fbase{mm, 0, 0, 0, xs, smax};
+  return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(base, fock, bonds, false),
+          base,                              plan_for(base, fresh, bonds, false), slots,
+          mixed,                             tile};
 }
 
 // ---------------------------------------------------------------------------
@@ -382,6 +427,16 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   d.nsub = ns; d.ncells = lat->n_cells > 0 ? lat->n_cells : N; d.flags = par->flags; d.nobs = w->nobs;
   d.mixed = par->precision == LECQMC_MIXED ? 1 : 0;
   d.ne[0] = ne[0]; d.ne[1] = ne[1]; d.mmax = w->mmax;
+  {
+    int tile, chunk;
+    shape_default(w->mmax, &tile, &chunk);
+    auto it = ctx->tuned.find(std::make_tuple(N, ne[0], ne[1], d.mixed));
+    if (it != ctx->tuned.end() && shape_valid(w->mmax, it->second.first, it->second.second)) {
+      tile = it->second.first;
+      chunk = it->second.second;
+    }
+    shape_apply(d, tile, chunk);
+  }
   d.seed = par->seed; d.wid = par->walker_id;
   // Ising decoupling in the spin channel: cosh(lambda) = exp(dtau U / 2)
   const double lambda = acosh(exp(par->dtau * par->U / 2.0));
@@ -537,7 +592,7 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
   const LaunchCfg cf = launch_cfg(&w, 1);
   for (int t = 0; t < n_sweeps; ++t) {
     HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.left, cf.mixed, st); }));
-    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.fwd, do_measure, cf.mixed, st); }));
+    HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.fwd, cf.tile, do_measure, cf.mixed, st); }));
     if (do_measure) HIPCHK(launch_measure(w->d_desc, 1, std::max(1, w->nblk - 1), cf.meas, st));
     HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.fock, cf.mixed, st); }));
   }
@@ -588,7 +643,7 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
     HIPCHK(timed(c, 0, [&] { return each([&](const Group &g) {
       return launch_left_stack(g.d, g.n, g.cf.left, g.cf.mixed, c->stream); }); }));
     HIPCHK(timed(c, 1, [&] { return each([&](const Group &g) {
-      return launch_forward(g.d, g.n, g.cf.fwd, do_measure, g.cf.mixed, c->stream); }); }));
+      return launch_forward(g.d, g.n, g.cf.fwd, g.cf.tile, do_measure, g.cf.mixed, c->stream); }); }));
     if (do_measure)
       HIPCHK(each([&](const Group &g) { return launch_measure(g.d, g.n, g.cf.slots, g.cf.meas, c->stream); }));
     HIPCHK(timed(c, 2, [&] { return each([&](const Group &g) {
@@ -658,7 +713,7 @@ extern "C" int lecqmc_batch_sweep(lecqmc_batch *b, int32_t n_sweeps, int32_t do_
       const WalkerDesc *d = g == 0 ? b->d : b->d + b->n64;
       const LaunchCfg &cf = g == 0 ? b->cf64 : b->cfmx;
       HIPCHK(launch_left_stack(d, gn, cf.left, cf.mixed, st));
-      HIPCHK(launch_forward(d, gn, cf.fwd, do_measure, cf.mixed, st));
+      HIPCHK(launch_forward(d, gn, cf.fwd, cf.tile, do_measure, cf.mixed, st));
       if (do_measure) HIPCHK(launch_measure(d, gn, cf.slots, cf.meas, st));
       HIPCHK(launch_fock(d, gn, cf.fock, cf.mixed, st));
     }
@@ -672,6 +727,161 @@ extern "C" int lecqmc_batch_destroy(lecqmc_batch *b) {
   (void)hipFree(b->d);
   for (lecqmc_walker *w : b->ws) w->batches -= 1;
   delete b;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// flip-chain shapes and the autotuner
+// ---------------------------------------------------------------------------
+extern "C" int lecqmc_get_shape(const lecqmc_walker *w, int32_t *tile, int32_t *chunk) {
+  if (!w || !tile || !chunk) return fail(LECQMC_EINVAL, "null argument");
+  *tile = w->h.tile;
+  *chunk = w->h.chunk;
+  return 0;
+}
+
+static int set_shape(lecqmc_walker *w, int tile, int chunk) {
+  shape_apply(w->h, tile, chunk);
+  HIPCHK(hipStreamSynchronize(w->ctx->stream));
+  HIPCHK(hipMemcpy(w->d_desc, &w->h, sizeof(WalkerDesc), hipMemcpyHostToDevice));
+  return 0;
+}
+
+extern "C" int lecqmc_set_shape(lecqmc_walker *w, int32_t tile, int32_t chunk) {
+  if (!w) return fail(LECQMC_EINVAL, "null walker");
+  if (!shape_valid(w->mmax, tile, chunk))
+    return fail(LECQMC_EINVAL, "shape (tile %d, chunk %d) not valid for Ne = %d", tile, chunk, w->mmax);
+  if (w->batches > 0) return fail(LECQMC_ESTATE, "walker belongs to %d batch(es)", w->batches);
+  HIPCHK(hipSetDevice(w->ctx->device));
+  return set_shape(w, tile, chunk);
+}
+
+// Every candidate shape runs one whole forward pass of every walker it is
+// valid for, from the same saved state (fields and scalars: the rest of a
+// walker's device state is rebuilt by the next sweep), timed per walker by
+// the kernel's own wall clock.  The state is restored afterwards, so tuning
+// leaves the Markov chains where they were.
+constexpr int kTiles = 4;
+extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *tile_out, int32_t *chunk_out,
+                               double *fwd_ms_out) {
+  if (!ws || n <= 0) return fail(LECQMC_EINVAL, "bad arguments");
+  lecqmc_ctx *c = ws[0] ? ws[0]->ctx : nullptr;
+  for (int t = 0; t < n; ++t) {
+    if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers must share one context");
+    if (ws[t]->batches > 0) return fail(LECQMC_ESTATE, "walker %d belongs to a batch", t);
+    for (int u = 0; u < t; ++u)
+      if (ws[u] == ws[t]) return fail(LECQMC_EINVAL, "a walker appears twice");
+  }
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  int rate_khz = 0;
+  HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+  if (rate_khz <= 0) return fail(LECQMC_EDEVICE, "no wall-clock rate");
+  // saved state: fields and scalars of every walker
+  std::vector<size_t> off(n + 1, 0);
+  for (int t = 0; t < n; ++t)
+    off[t + 1] = off[t] + align256((size_t)ws[t]->L * ws[t]->N) + align256(sizeof(Scalars));
+  char *snap = nullptr;
+  HIPCHK(hipMalloc(&snap, off[n]));
+  std::vector<WalkerDesc> hd;
+  WalkerDesc *dd = nullptr;
+  hipError_t e = hipMalloc(&dd, sizeof(WalkerDesc) * n);
+  std::vector<int> cur_tile(n), cur_chunk(n);
+  // per shape key and candidate: summed milliseconds of its walkers (< 0: not run)
+  using Key = std::tuple<int, int, int, int>;
+  auto key_of = [](const lecqmc_walker *w) { return std::make_tuple(w->N, w->ne[0], w->ne[1], w->h.mixed); };
+  std::map<Key, std::vector<double>> tot;
+  std::vector<std::vector<double>> wms(n, std::vector<double>(4 * kTiles, -1.0));
+  for (int t = 0; t < n; ++t) tot[key_of(ws[t])].assign(4 * kTiles, -1.0);
+  auto restore = [&](int t) {
+    const size_t nf = (size_t)ws[t]->L * ws[t]->N;
+    hipError_t r = hipMemcpyAsync(ws[t]->h.s, snap + off[t], nf, hipMemcpyDeviceToDevice, st);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(ws[t]->h.sc, snap + off[t] + align256(nf), sizeof(Scalars), hipMemcpyDeviceToDevice, st);
+    return r;
+  };
+  for (int t = 0; t < n; ++t) {
+    cur_tile[t] = ws[t]->h.tile;
+    cur_chunk[t] = ws[t]->h.chunk;
+  }
+  // the left states of the current fields (they do not depend on the shape)
+  for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+    std::vector<lecqmc_walker *> g;
+    for (int t = 0; t < n; ++t)
+      if (ws[t]->h.mixed == pass) g.push_back(ws[t]);
+    if (g.empty()) continue;
+    hd.clear();
+    for (auto *w : g) hd.push_back(w->h);
+    e = hipMemcpy(dd, hd.data(), sizeof(WalkerDesc) * hd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_left_stack(dd, (int)g.size(), launch_cfg(g.data(), (int)g.size()).left, pass, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  for (int t = 0; t < n && e == hipSuccess; ++t) {
+    const size_t nf = (size_t)ws[t]->L * ws[t]->N;
+    e = hipMemcpyAsync(snap + off[t], ws[t]->h.s, nf, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(snap + off[t] + align256(nf), ws[t]->h.sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st);
+  }
+  static const int tiles[kTiles] = {1, 2, 4, 0}, chunks[4] = {4, 8, 16, 32};
+  for (int ti = 0; ti < kTiles && e == hipSuccess; ++ti)
+    for (int ci = 0; ci < 4 && e == hipSuccess; ++ci)
+      for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        std::vector<lecqmc_walker *> g;
+        std::vector<int> idx;
+        for (int t = 0; t < n; ++t)
+          if (ws[t]->h.mixed == pass && shape_valid(ws[t]->mmax, tiles[ti], chunks[ci])) {
+            g.push_back(ws[t]);
+            idx.push_back(t);
+          }
+        if (g.empty()) continue;
+        hd.clear();
+        for (auto *w : g) {
+          shape_apply(w->h, tiles[ti], chunks[ci]);
+          hd.push_back(w->h);
+        }
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipMemcpy(dd, hd.data(), sizeof(WalkerDesc) * hd.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+          const LaunchCfg cf = launch_cfg(g.data(), (int)g.size());
+          e = launch_forward(dd, (int)g.size(), cf.fwd, cf.tile, 0, pass, st);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        for (size_t q = 0; q < g.size() && e == hipSuccess; ++q) {
+          long long ticks = 0;
+          e = hipMemcpy(&ticks, &g[q]->h.sc->fwd_ticks, sizeof ticks, hipMemcpyDeviceToHost);
+          const double ms = (double)ticks / (double)rate_khz;
+          const int t = idx[q], cand = ti * 4 + ci;
+          if (e == hipSuccess) {
+            wms[t][cand] = ms;
+            double &sum = tot[key_of(ws[t])][cand];
+            sum = (sum < 0.0 ? 0.0 : sum) + ms;
+            e = restore(t);
+          }
+        }
+      }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dd);
+  (void)hipFree(snap);
+  // one shape per key: the candidate with the least summed time over the
+  // key's walkers (the current shapes if tuning failed)
+  const bool ok = e == hipSuccess;
+  std::map<Key, int> best;
+  for (auto &kv : tot) {
+    int bc = -1;
+    for (int q = 0; q < 4 * kTiles; ++q)
+      if (kv.second[q] >= 0.0 && (bc < 0 || kv.second[q] < kv.second[bc])) bc = q;
+    best[kv.first] = bc;
+  }
+  for (int t = 0; t < n; ++t) {
+    const int bc = ok ? best[key_of(ws[t])] : -1;
+    const int tile = bc >= 0 ? tiles[bc / 4] : cur_tile[t], chunk = bc >= 0 ? chunks[bc % 4] : cur_chunk[t];
+    if (int rc = set_shape(ws[t], tile, chunk)) return rc;
+    if (bc >= 0) c->tuned[key_of(ws[t])] = {tile, chunk};
+    if (tile_out) tile_out[t] = tile;
+    if (chunk_out) chunk_out[t] = chunk;
+    if (fwd_ms_out) fwd_ms_out[t] = bc >= 0 ? wms[t][bc] : -1.0;
+  }
+  if (e != hipSuccess) return fail(LECQMC_EDEVICE, "autotune: %s", hipGetErrorString(e));
   return 0;
 }
 

@@ -26,6 +26,7 @@ struct Scalars {
   double fresh_logw;            // written by the fresh-weight kernel
   int fresh_sign;
   int pad;
+  long long fwd_ticks;          // wall-clock ticks of the last forward pass of this walker
   double dbg[4];
 };
 
@@ -35,6 +36,10 @@ struct WalkerDesc {
   int mixed;                    // 1: FP32 slice propagation (LECQMC_MIXED)
   int ne[2];
   int mmax;                     // max(ne[0], ne[1], 1): stride of the per-level Fock scratch
+  // shape of the flip chain (set by the host: default by Ne, or autotuned)
+  int tile;                     // register tile T (Ne <= 8T held in registers) or 0 (inverse in LDS)
+  int chunk;                    // sites per staged chunk, 4..32
+  int xld;                      // row stride of the staged rows: 8T, or mmax when tile = 0
   uint64_t seed, wid;
   double elam, emlam;           // exp(+lambda), exp(-lambda)
   double delta_dn_s, delta_up_s;// Delta for sigma*s = +1: exp(-2 lambda) - 1 ; sigma*s = -1: exp(2 lambda) - 1
@@ -80,13 +85,20 @@ struct WalkerDesc {
   Scalars *sc;
 };
 
-// LDS plan of one launch: the largest Ne (mm), Slater blocks kept resident
-// (phi_elems doubles, 0 = streamed), right-row staging buffers (streamed
-// forward pass only) and the compact bond tables (bond_words, 0 = read from
-// device memory).
+// LDS plan of one launch: the largest Ne (mm), the room for resident Slater
+// blocks (phi_elems doubles; a walker whose blocks fit keeps them there, the
+// others stream them), right-row staging buffers (forward pass with a
+// streamed walker), the compact bond tables (bond_words, 0 = read from device
+// memory) and the flip-chain staging area (xs_elems doubles for the largest
+// 4 * chunk * xld of the launch, smax = its largest chunk; 0 outside the
+// forward pass).
 struct LdsPlan {
-  int mm, phi_elems, stage_ps, bond_words;
+  int mm, phi_elems, stage_ps, bond_words, xs_elems, smax;
 };
+// LDS doubles that a walker's resident blocks of `entries` elements need
+__host__ __device__ inline long phi_doubles(long entries, int elem_bytes) {
+  return (entries * elem_bytes + 7) / 8;
+}
 constexpr size_t kLdsLimit = 163840;
 constexpr int kMaxCoef = 16;
 size_t lds_bytes(const LdsPlan &p);
@@ -96,7 +108,10 @@ hipError_t launch_fresh_weight(const WalkerDesc *d_descs, int n, LdsPlan p, int 
 // mixed != 0: FP32 storage and propagation of the Slater blocks, stored left
 // states and Fock columns (every walker of the launch must be mixed)
 hipError_t launch_left_stack(const WalkerDesc *d_descs, int n, LdsPlan p, int mixed, hipStream_t st);
-hipError_t launch_forward(const WalkerDesc *d_descs, int n, LdsPlan p, int do_measure, int mixed, hipStream_t st);
+// tile: the chain shape shared by every walker of the launch (1, 2, 4 or 0),
+// or -1 when they differ (each walker's own shape is dispatched in the kernel)
+hipError_t launch_forward(const WalkerDesc *d_descs, int n, LdsPlan p, int tile, int do_measure, int mixed,
+                          hipStream_t st);
 hipError_t launch_fock(const WalkerDesc *d_descs, int n, LdsPlan p, int mixed, hipStream_t st);
 hipError_t launch_measure(const WalkerDesc *d_descs, int n, int slots, LdsPlan p, hipStream_t st);
 hipError_t launch_green(const WalkerDesc *d_desc, int max_ne, int boundary, int spin, double *G, hipStream_t st);

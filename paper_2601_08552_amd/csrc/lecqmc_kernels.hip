@@ -60,8 +60,8 @@ struct Lds {
   double *B;      // mm^2  triangular inverse / output
   double *vec;    // 8*64  small vectors
   double *uw;     // 2*64  flip-chain column vectors (Ne > 32 path)
-  double *xs;     // [2 buf][2 spin][S][mm]  staged left rows
-  double *ps;     // [2 buf][2 spin][S][mm]  staged right rows (streamed mode)
+  double *xs;     // [2 buf][2 spin][S][xld] staged left rows
+  double *ps;     // [2 buf][2 spin][S][xld] staged right rows (streamed mode)
   double *us;     // [2 buf][S]              staged uniforms
   double *dl;     // [2 buf][2 spin][S]      staged flip factors Delta
   int8_t *fs;     // [2 buf][S]              staged Ising fields
@@ -72,17 +72,14 @@ struct Lds {
   int *cs;        // colour offsets copied into LDS (iscal + 16), or nullptr
 };
 
-__host__ __device__ inline int chunk_size(int mm) { return mm <= 16 ? 32 : (mm <= 32 ? 16 : 4); }
-
-__host__ __device__ inline size_t lds_doubles_fixed(int mm, int stage_ps) {
-  if (mm < 1) mm = 1;
-  const size_t S = chunk_size(mm);
-  return 256 + 64 + 4 * (size_t)mm * mm + 8 * 64 + 2 * 64 + (stage_ps ? 2 : 1) * (2 * 2 * S * mm) + 2 * S + 4 * S +
+__host__ __device__ inline size_t lds_doubles_fixed(const LdsPlan &p) {
+  const size_t mm = p.mm < 1 ? 1 : p.mm, S = p.smax > 0 ? p.smax : 0;
+  return 256 + 64 + 4 * mm * mm + 8 * 64 + 2 * 64 + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S + 4 * S +
          (2 * S + 7) / 8;
 }
 
 size_t lds_bytes(const LdsPlan &p) {
-  const size_t d = lds_doubles_fixed(p.mm, p.stage_ps) + (size_t)p.phi_elems + ((size_t)p.bond_words + 1) / 2;
+  const size_t d = lds_doubles_fixed(p) + (size_t)p.phi_elems + ((size_t)p.bond_words + 1) / 2;
   return d * sizeof(double) + 320 * sizeof(int);
 }
 
@@ -90,7 +87,7 @@ extern __shared__ double lds_raw[];
 
 __device__ Lds carve(const LdsPlan &pl) {
   const int mm = pl.mm < 1 ? 1 : pl.mm;
-  const int S = chunk_size(mm);
+  const int S = pl.smax > 0 ? pl.smax : 0;
   Lds L;
   double *p = lds_raw;
   L.red = p; p += 256;
@@ -101,8 +98,8 @@ __device__ Lds carve(const LdsPlan &pl) {
   L.B = p; p += mm * mm;
   L.vec = p; p += 8 * 64;
   L.uw = p; p += 2 * 64;
-  L.xs = p; p += 2 * 2 * S * mm;
-  L.ps = pl.stage_ps ? p : nullptr; p += pl.stage_ps ? 2 * 2 * S * mm : 0;
+  L.xs = p; p += pl.xs_elems;
+  L.ps = pl.stage_ps ? p : nullptr; p += pl.stage_ps ? pl.xs_elems : 0;
   L.us = p; p += 2 * S;
   L.dl = p; p += 4 * S;
   L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
@@ -115,7 +112,7 @@ __device__ Lds carve(const LdsPlan &pl) {
   return L;
 }
 __device__ Lds carve(int mm, int phi_elems) {
-  LdsPlan pl{mm, phi_elems, 1, 0};
+  LdsPlan pl{mm, phi_elems, 1, 0, 0, 0};
   return carve(pl);
 }
 
@@ -215,7 +212,7 @@ __device__ __forceinline__ void bond_get(const WalkerDesc &w, const BondSrc &bs,
 // copy the compact bond tables of walker w into LDS (all threads)
 // copy the compact bond tables of walker w into LDS, and the colour offsets
 // (read at every colour pass) when there are at most 47 colours (all threads)
-__device__ void load_bonds(const WalkerDesc &w, Lds &L, int plan_words) {
+__device__ __forceinline__ void load_bonds(const WalkerDesc &w, Lds &L, int plan_words) {
   if (w.ncol + 1 <= 48) {
     for (int t = TID; t <= w.ncol; t += kThreads) L.iscal[16 + t] = w.col_start[t];
     L.cs = L.iscal + 16;
@@ -1209,7 +1206,8 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *__r
   double la = 0.0;
   int sg = 1;
   for (int sp = 0; sp < 2; ++sp) {
-    double *Phi = L.phi ? L.phi : w.PhiR[sp];
+    const bool res = L.phi != nullptr && (long)w.N * w.ne[sp] <= (long)pl.phi_elems;
+    double *Phi = res ? L.phi : w.PhiR[sp];
     la += right_stack(w, sp, L, Phi);
     double l2;
     int s2;
@@ -1244,7 +1242,8 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__res
   {
     const int sp = blockIdx.x & 1;
     const int m = w.ne[sp];
-    F *Y = L.phi ? reinterpret_cast<F *>(L.phi) : reinterpret_cast<F *>(w.X[sp]);
+    const bool res = L.phi != nullptr && phi_doubles((long)N * m, (int)sizeof(F)) <= (long)pl.phi_elems;
+    F *Y = res ? reinterpret_cast<F *>(L.phi) : reinterpret_cast<F *>(w.X[sp]);
     F *LX = reinterpret_cast<F *>(w.LX[sp]);
     fill_P(w, sp, Y);
     copy_global(w.LS[sp] + (size_t)w.nblk * N * m, Y, (size_t)N * m);
@@ -1268,13 +1267,11 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__res
 // (FP64, or FP32 for mixed-precision walkers).  Ratios, inverses, QR and
 // weights are FP64 in both.
 template <int TSEL, typename F>
-__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restrict__ descs, LdsPlan pl, int want_aw) {
-  const WalkerDesc &w = descs[blockIdx.x];
-  Lds L = carve(pl);
-  const int mm = pl.mm < 1 ? 1 : pl.mm;
-  load_bonds(w, L, pl.bond_words);
+__device__ __forceinline__ void forward_walker(const WalkerDesc &w, Lds &L, const LdsPlan &pl, int want_aw) {
   const int N = w.N, n = w.nblk;
-  const bool resident = L.phi != nullptr;
+  const int xld = w.xld;
+  const bool resident =
+      L.phi != nullptr && phi_doubles((long)N * (w.ne[0] + w.ne[1]), (int)sizeof(F)) <= (long)pl.phi_elems;
   const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
   F *const phi[2] = {resident ? reinterpret_cast<F *>(L.phi) : reinterpret_cast<F *>(w.PhiR[0]),
                      resident ? reinterpret_cast<F *>(L.phi) + (size_t)N * w.ne[0] : reinterpret_cast<F *>(w.PhiR[1])};
@@ -1300,7 +1297,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
       if (m > 0 && !gj_inverse(L.A, sp ? L.Ms1 : L.Ms0, m, L, &la, &sg))
         if (TID == 0) w.sc->status |= 4;
     }
-    forward_block<TSEL, F>(w, k, sweep, L, phi, resident, mm, acc);
+    forward_block<TSEL, F>(w, k, sweep, L, phi, resident, xld, acc);
     // block end: diagonal of A from the updated inverse, kept for the wrap check
     if (k < n && want_aw)
       for (int sp = 0; sp < 2; ++sp) {
@@ -1348,6 +1345,31 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
     sc->flip_acc += acc.nacc;
     sc->sweep = sweep;
   }
+}
+
+// One workgroup per walker.  TSEL >= 0: every walker of the launch has that
+// chain shape (register tile T, or 0 for the LDS inverse); TSEL < 0: each
+// walker's own shape is dispatched here, so walkers of different Ne share a
+// launch without changing each other's arithmetic.  The walker's wall-clock
+// time of the pass is recorded for the autotuner.
+template <int TSEL, typename F>
+__global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restrict__ descs, LdsPlan pl, int want_aw) {
+  const WalkerDesc &w = descs[blockIdx.x];
+  const long long t0 = wall_clock64();
+  Lds L = carve(pl);
+  L.S = w.chunk;
+  load_bonds(w, L, pl.bond_words);
+  if constexpr (TSEL >= 0) {
+    forward_walker<TSEL, F>(w, L, pl, want_aw);
+  } else {
+    switch (w.tile) {
+      case 1: forward_walker<1, F>(w, L, pl, want_aw); break;
+      case 2: forward_walker<2, F>(w, L, pl, want_aw); break;
+      case 4: forward_walker<4, F>(w, L, pl, want_aw); break;
+      default: forward_walker<0, F>(w, L, pl, want_aw); break;
+    }
+  }
+  if (TID == 0) w.sc->fwd_ticks = wall_clock64() - t0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2017,7 +2039,16 @@ hipError_t launch_left_stack(const WalkerDesc *d, int n, LdsPlan p, int mixed, h
   }
   return hipGetLastError();
 }
-// register tile of the flip chain chosen by the largest Ne of the launch
+hipError_t launch_measure(const WalkerDesc *d, int n, int slots, LdsPlan p, hipStream_t st) {
+  p = clamp_plan(p);
+  const size_t b = lds_bytes(p);
+  lds_attr(k_measure, b);
+  hipLaunchKernelGGL(k_measure, dim3(n * slots), dim3(kThreads), b, st, d, p, slots);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_measure_sum, dim3(n), dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
 template <int TSEL>
 static hipError_t launch_forward_t(const WalkerDesc *d, int n, LdsPlan p, int want_aw, int mixed, hipStream_t st) {
   const size_t b = lds_bytes(p);
@@ -2030,22 +2061,15 @@ static hipError_t launch_forward_t(const WalkerDesc *d, int n, LdsPlan p, int wa
   }
   return hipGetLastError();
 }
-hipError_t launch_measure(const WalkerDesc *d, int n, int slots, LdsPlan p, hipStream_t st) {
+hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int tile, int do_measure, int mixed, hipStream_t st) {
   p = clamp_plan(p);
-  const size_t b = lds_bytes(p);
-  lds_attr(k_measure, b);
-  hipLaunchKernelGGL(k_measure, dim3(n * slots), dim3(kThreads), b, st, d, p, slots);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_measure_sum, dim3(n), dim3(kThreads), 0, st, d);
-  return hipGetLastError();
-}
-hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int do_measure, int mixed, hipStream_t st) {
-  p = clamp_plan(p);
-  if (p.mm <= 8) return launch_forward_t<1>(d, n, p, do_measure, mixed, st);
-  if (p.mm <= 16) return launch_forward_t<2>(d, n, p, do_measure, mixed, st);
-  if (p.mm <= 32) return launch_forward_t<4>(d, n, p, do_measure, mixed, st);
-  return launch_forward_t<0>(d, n, p, do_measure, mixed, st);
+  switch (tile) {
+    case 1: return launch_forward_t<1>(d, n, p, do_measure, mixed, st);
+    case 2: return launch_forward_t<2>(d, n, p, do_measure, mixed, st);
+    case 4: return launch_forward_t<4>(d, n, p, do_measure, mixed, st);
+    case 0: return launch_forward_t<0>(d, n, p, do_measure, mixed, st);
+    default: return launch_forward_t<-1>(d, n, p, do_measure, mixed, st);
+  }
 }
 hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStream_t st) {
   p = clamp_plan(p);

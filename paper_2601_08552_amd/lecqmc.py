@@ -32,6 +32,7 @@ EXPORTED = [
     "lecqmc_measure", "lecqmc_reset_measure", "lecqmc_get_stats", "lecqmc_get_state",
     "lecqmc_set_state", "lecqmc_green", "lecqmc_flip_ratio", "lecqmc_swap_ratio", "lecqmc_last_error",
     "lecqmc_batch_create", "lecqmc_batch_sweep", "lecqmc_batch_destroy",
+    "lecqmc_get_shape", "lecqmc_set_shape", "lecqmc_autotune",
 ]
 
 
@@ -123,6 +124,10 @@ def load():
             "lecqmc_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp)]),
             "lecqmc_batch_sweep": (C.c_int, [vp, i32, i32]),
             "lecqmc_batch_destroy": (C.c_int, [vp]),
+            "lecqmc_get_shape": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32)]),
+            "lecqmc_set_shape": (C.c_int, [vp, i32, i32]),
+            "lecqmc_autotune": (C.c_int, [C.POINTER(vp), i32, C.POINTER(i32), C.POINTER(i32),
+                                          C.POINTER(C.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -287,6 +292,17 @@ class Walker:
                                        None if ou is None else ou.ctypes.data,
                                        None if od is None else od.ctypes.data, sweep_counter))
 
+    @property
+    def shape(self):
+        """(tile, chunk) of the flip chain: register tile T (Ne <= 8T) or 0
+        for the inverse in LDS, and the sites per staged chunk."""
+        t, c = C.c_int32(), C.c_int32()
+        _check(load().lecqmc_get_shape(self.h, C.byref(t), C.byref(c)))
+        return int(t.value), int(c.value)
+
+    def set_shape(self, tile, chunk):
+        _check(load().lecqmc_set_shape(self.h, tile, chunk))
+
     def green(self, boundary, spin):
         G = np.zeros((self.N, self.N))
         _check(load().lecqmc_green(self.h, boundary, spin, G.ctypes.data))
@@ -301,6 +317,17 @@ class Walker:
         r = C.c_double()
         _check(load().lecqmc_swap_ratio(self.h, spin, k, j, C.byref(r)))
         return r.value
+
+
+def autotune(walkers):
+    """Time every valid flip-chain shape on these walkers (their chains are
+    not advanced); walkers of one (N, Ne_up, Ne_dn, precision) key get the
+    shape with the least total time.  Returns [(tile, chunk, ms)] per walker."""
+    n = len(walkers)
+    arr = (C.c_void_p * n)(*[w.h for w in walkers])
+    tl, ch, ms = (C.c_int32 * n)(), (C.c_int32 * n)(), (C.c_double * n)()
+    _check(load().lecqmc_autotune(arr, n, tl, ch, ms))
+    return [(int(tl[t]), int(ch[t]), float(ms[t])) for t in range(n)]
 
 
 def sweep_batch(walkers, n_sweeps=1, measure=False):
