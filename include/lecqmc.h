@@ -59,7 +59,7 @@ extern "C" {
 #define LECQMC_NO_FOCK 1      /* flags: skip the particle-hole swap phase             */
 #define LECQMC_NO_FLIPS 2     /* flags: skip the Ising flips (fields frozen)          */
 
-#define LECQMC_MAX_NE 64      /* largest particle number per spin handled on device  */
+#define LECQMC_MAX_NE 256     /* largest particle number per spin handled on device  */
 
 typedef struct lecqmc_ctx lecqmc_ctx;
 typedef struct lecqmc_walker lecqmc_walker;

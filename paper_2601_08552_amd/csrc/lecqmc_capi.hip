@@ -96,7 +96,7 @@ static bool shape_valid(int mmax, int tile, int chunk) {
   if (tile > 0 && mmax > 8 * tile) return false;
   if (!(chunk == 4 || chunk == 8 || chunk == 16 || chunk == 32)) return false;
   // both staging buffers (streamed walker) must fit next to the fixed layout
-  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk};
+  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, mmax > kLdsNe ? 1 : 0};
   return lds_bytes(p) <= kLdsLimit;
 }
 static void shape_apply(WalkerDesc &h, int tile, int chunk) {
@@ -163,7 +163,9 @@ static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
     if (w->h.tile != tile) tile = -1;
   }
   if (!compact) bonds = 0;
-  const LdsPlan base{mm, 0, 0, 0, 0, 0}, fbase{mm, 0, 0, 0, xs, smax};
+  const int gm = mm > kLdsNe ? 1 : 0;
+  if (gm) slots = 1;   // one estimator workgroup per walker: the work matrices are one per walker
+  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm}, fbase{mm, 0, 0, 0, xs, smax, gm};
   return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(base, fock, bonds, false),
           base,                              plan_for(base, fresh, bonds, false), slots,
           mixed,                             tile};
@@ -219,7 +221,7 @@ struct Plan {
   size_t off_sc, off_desc, off_s, off_occ[2], off_LS[2], off_LX[2], off_RQ[2], off_RV[2], off_Minv[2], off_PhiR[2], off_X[2],
       off_T[2], off_Aw[2], off_mpart, off_mscr, off_fq, off_fw, off_fVp, off_fgc, off_fgs, off_fv, off_frho, off_fmark, off_obs,
       off_dbg, off_col, off_bi, off_bj, off_bdiag, off_boff, off_bh, off_epsf, off_eps, off_sub, off_bij, off_bci,
-      off_coef;
+      off_coef, off_bigm;
   size_t mscr_stride;
   size_t total;
 };
@@ -284,6 +286,7 @@ static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int
   p.off_bij = take(sizeof(int) * nbonds);
   p.off_bci = take(nbonds);
   p.off_coef = take(sizeof(double) * 2 * kMaxCoef);
+  p.off_bigm = take(sizeof(double) * 8 * (size_t)mmax * mmax);
   p.total = o;
   return p;
 }
@@ -472,6 +475,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   d.fmark = (int *)(base + p.off_fmark);
   d.obs = (double *)(base + p.off_obs);
   d.dbg = (double *)(base + p.off_dbg);
+  d.bigm = (double *)(base + p.off_bigm);
   int *col_start = (int *)(base + p.off_col);
   int *bi = (int *)(base + p.off_bi);
   int *bj = (int *)(base + p.off_bj);
@@ -593,7 +597,7 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
   for (int t = 0; t < n_sweeps; ++t) {
     HIPCHK(timed(c, 0, [&] { return launch_left_stack(w->d_desc, 1, cf.left, cf.mixed, st); }));
     HIPCHK(timed(c, 1, [&] { return launch_forward(w->d_desc, 1, cf.fwd, cf.tile, do_measure, cf.mixed, st); }));
-    if (do_measure) HIPCHK(launch_measure(w->d_desc, 1, std::max(1, w->nblk - 1), cf.meas, st));
+    if (do_measure) HIPCHK(launch_measure(w->d_desc, 1, cf.slots, cf.meas, st));
     HIPCHK(timed(c, 2, [&] { return launch_fock(w->d_desc, 1, cf.fock, cf.mixed, st); }));
   }
   return 0;

@@ -7,7 +7,8 @@
 namespace lecqmc {
 
 constexpr int kThreads = 256;   // one workgroup (4 wave64) per walker
-constexpr int kMaxNe = 64;      // particles per spin held in LDS-resident Ne x Ne blocks
+constexpr int kMaxNe = 256;     // particles per spin
+constexpr int kLdsNe = 64;      // largest Ne whose Ne x Ne work matrices are kept in LDS
 
 // counter-based generator streams (shared layout with the walker's key)
 enum Stream : uint32_t { kFlip = 1, kSwapK = 2, kSwapJ = 3, kSwapAcc = 4, kInitField = 5, kInitOcc = 6 };
@@ -82,10 +83,13 @@ struct WalkerDesc {
   int *fmark;                   // [2][N] occupancy marks / permutation scratch
   double *obs;                  // [nobs]
   double *dbg;                  // [N*N] parity-surface output (N <= dbg_n) else [8]
+  double *bigm;                 // [2 slots][4][mmax^2] the Ne x Ne work matrices of a launch whose
+                                // largest Ne exceeds kLdsNe (slot = spin in per-spin kernels)
   Scalars *sc;
 };
 
-// LDS plan of one launch: the largest Ne (mm), the room for resident Slater
+// LDS plan of one launch: the largest Ne (mm; above kLdsNe the Ne x Ne work
+// matrices move to device memory, gm = 1), the room for resident Slater
 // blocks (phi_elems doubles; a walker whose blocks fit keeps them there, the
 // others stream them), right-row staging buffers (forward pass with a
 // streamed walker), the compact bond tables (bond_words, 0 = read from device
@@ -94,6 +98,7 @@ struct WalkerDesc {
 // forward pass).
 struct LdsPlan {
   int mm, phi_elems, stage_ps, bond_words, xs_elems, smax;
+  int gm;   // 1: the Ne x Ne work matrices live in each walker's bigm, not in LDS
 };
 // LDS doubles that a walker's resident blocks of `entries` elements need
 __host__ __device__ inline long phi_doubles(long entries, int elem_bytes) {

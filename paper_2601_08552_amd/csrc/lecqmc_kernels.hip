@@ -58,8 +58,8 @@ struct Lds {
   double *Ms1;    // mm^2  inverse, spin down (Fock phase: permuted inverse)
   double *A;      // mm^2  Gram / Cholesky / pivot work (Fock phase: reduced inverse)
   double *B;      // mm^2  triangular inverse / output
-  double *vec;    // 8*64  small vectors
-  double *uw;     // 2*64  flip-chain column vectors (Ne > 32 path)
+  double *vec;    // 8*vs  small vectors
+  double *uw;     // 4*vs  u and w of an accepted site per spin (LDS-inverse chain)
   double *xs;     // [2 buf][2 spin][S][xld] staged left rows
   double *ps;     // [2 buf][2 spin][S][xld] staged right rows (streamed mode)
   double *us;     // [2 buf][S]              staged uniforms
@@ -70,12 +70,14 @@ struct Lds {
   int S;          // sites per staged chunk
   bool bonds_ok;  // the walker's bond tables were copied into LDS
   int *cs;        // colour offsets copied into LDS (iscal + 16), or nullptr
+  int vs;         // length of each small vector: max(64, largest Ne of the launch)
 };
 
+__host__ __device__ inline int vec_len(int mm) { return mm > 64 ? mm : 64; }
 __host__ __device__ inline size_t lds_doubles_fixed(const LdsPlan &p) {
-  const size_t mm = p.mm < 1 ? 1 : p.mm, S = p.smax > 0 ? p.smax : 0;
-  return 256 + 64 + 4 * mm * mm + 8 * 64 + 2 * 64 + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S + 4 * S +
-         (2 * S + 7) / 8;
+  const size_t mm = p.mm < 1 ? 1 : p.mm, S = p.smax > 0 ? p.smax : 0, vs = vec_len((int)mm);
+  return 256 + 64 + (p.gm ? 0 : 4 * mm * mm) + 8 * vs + 4 * vs + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S +
+         4 * S + (2 * S + 7) / 8;
 }
 
 size_t lds_bytes(const LdsPlan &p) {
@@ -90,14 +92,20 @@ __device__ Lds carve(const LdsPlan &pl) {
   const int S = pl.smax > 0 ? pl.smax : 0;
   Lds L;
   double *p = lds_raw;
+  const int vs = vec_len(mm);
   L.red = p; p += 256;
   L.scal = p; p += 64;
-  L.Ms0 = p; p += mm * mm;
-  L.Ms1 = p; p += mm * mm;
-  L.A = p; p += mm * mm;
-  L.B = p; p += mm * mm;
-  L.vec = p; p += 8 * 64;
-  L.uw = p; p += 2 * 64;
+  if (pl.gm) {
+    L.Ms0 = L.Ms1 = L.A = L.B = nullptr;   // bound per walker by bind_mats
+  } else {
+    L.Ms0 = p; p += mm * mm;
+    L.Ms1 = p; p += mm * mm;
+    L.A = p; p += mm * mm;
+    L.B = p; p += mm * mm;
+  }
+  L.vs = vs;
+  L.vec = p; p += 8 * vs;
+  L.uw = p; p += 4 * vs;
   L.xs = p; p += pl.xs_elems;
   L.ps = pl.stage_ps ? p : nullptr; p += pl.stage_ps ? pl.xs_elems : 0;
   L.us = p; p += 2 * S;
@@ -111,10 +119,19 @@ __device__ Lds carve(const LdsPlan &pl) {
   L.cs = nullptr;
   return L;
 }
-__device__ Lds carve(int mm, int phi_elems) {
-  LdsPlan pl{mm, phi_elems, 1, 0, 0, 0};
-  return carve(pl);
+// Ne x Ne work matrices in device memory (plans with gm = 1): slot 0 for
+// kernels with one workgroup per walker, the spin for those with one per
+// (walker, spin).  The matrices are addressed with the walker's own Ne.
+__device__ __forceinline__ void bind_mats(Lds &L, const WalkerDesc &w, const LdsPlan &pl, int slot) {
+  if (!pl.gm) return;
+  const size_t q = (size_t)w.mmax * w.mmax;
+  double *base = w.bigm + (size_t)slot * 4 * q;
+  L.Ms0 = base;
+  L.Ms1 = base + q;
+  L.A = base + 2 * q;
+  L.B = base + 3 * q;
 }
+__device__ __forceinline__ LdsPlan parity_plan(int mm) { return LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0}; }
 
 #define TID (static_cast<int>(threadIdx.x))
 #define SYNC() __syncthreads()
@@ -531,7 +548,7 @@ __device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logab
   for (int t = TID; t < m * m; t += kThreads) Minv[t] = (t / m == t % m) ? 1.0 : 0.0;
   if (TID == 0) { L.scal[2] = 0.0; L.iscal[1] = 1; L.iscal[2] = 0; }
   SYNC();
-  double *fac = L.vec + 7 * 64;
+  double *fac = L.vec + 7 * L.vs;
   for (int c = 0; c < m; ++c) {
     if (TID == 0) {
       int p = c;
@@ -751,15 +768,69 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
   return mask;
 }
 
-// LDS version for 32 < Ne <= 64: lane h of a half owns rows/columns h, h+32
-// of its spin's inverse, which stays in LDS (Ms0 / Ms1).
+// Version with the inverse in memory (LDS for Ne <= 64, the walker's device
+// scratch above), for any Ne.  The inverse M (row-major) is kept together
+// with a column-major copy MT for the block, so that every lane walks
+// consecutive addresses: lane h of a half owns rows and columns h, h + 32, ...
+// of its spin's inverse, forms u_h = M[h,:] x from MT and w_h = p M[:,h]
+// from M, and takes the rank-1 update of column h of M and of column h of MT
+// (row h of M) with the same fused products, so the two stay exact transposes.
+// sum_b A[b * sa] x[b] over b < m in blocks of 8 (eight loads in flight,
+// eight independent accumulators)
+template <typename PA, typename PX>
+__device__ __forceinline__ double dot8(PA A, int sa, PX x, int m) {
+  double t[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) t[e] = 0.0;
+  int b = 0;
+  for (; b + 8 <= m; b += 8) {
+    double av[8], xv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      av[e] = A[(b + e) * sa];
+      xv[e] = (double)x[b + e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = fma(av[e], xv[e], t[e]);
+  }
+  for (; b < m; ++b) t[0] = fma(A[b * sa], (double)x[b], t[0]);
+  return ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+}
+// A[b * sa] = fma(-k_b, v_b, A[b * sa]) for b < m in blocks of 8, with
+// k_b = kc * kv[b] (kc alone when kv is null) and v_b = v[b] (vc when v is null)
+__device__ __forceinline__ void axpy8(double *A, int sa, double kc, const double *kv, const double *v, double vc,
+                                      int m) {
+  int b = 0;
+  for (; b + 8 <= m; b += 8) {
+    double av[8], vv[8], kk[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      av[e] = A[(b + e) * sa];
+      vv[e] = v ? v[b + e] : vc;
+      kk[e] = kv ? kc * kv[b + e] : kc;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) A[(b + e) * sa] = fma(-kk[e], vv[e], av[e]);
+  }
+  for (; b < m; ++b) A[b * sa] = fma(-(kv ? kc * kv[b] : kc), v ? v[b] : vc, A[b * sa]);
+}
+
+// Version with the inverse in memory (LDS for Ne <= 64, the walker's device
+// scratch above), for any Ne.  The inverse M (row-major) is kept together
+// with a column-major copy MT for the block, so that every lane walks
+// consecutive addresses: lane h of a half owns rows and columns h, h + 32, ...
+// of its spin's inverse, forms u_h = M[h,:] x from MT and w_h = p M[:,h]
+// from M, and takes the rank-1 update of column h of M and of column h of MT
+// (row h of M) with the same fused products, so the two stay exact transposes.
 template <typename PE>
 __device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *xsb, int mm, const PE *prow,
                                     int ldp, const double *usb, const int8_t *fsb, int cnt, int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31;
   const int m = w.ne[sp];
-  double *Ms = sp ? L.Ms1 : L.Ms0;
-  double *wsh = L.uw + sp * 64;
+  double *M = sp ? L.Ms1 : L.Ms0;
+  double *MT = sp ? L.B : L.A;
+  double *ush = L.uw + sp * 2 * L.vs;   // u of the current site, then w on acceptance
+  double *wsh = ush + L.vs;
   const double *xsp = xsb + sp * S * mm;
   unsigned mask = 0;
   for (int r = 0; r < cnt; ++r) {
@@ -768,42 +839,26 @@ __device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *x
     const int sv = fsb[r];
     const int ss = sp == 0 ? sv : -sv;
     const double delta = ss > 0 ? w.delta_dn_s : w.delta_up_s;
-    double u0 = 0.0, u1 = 0.0, part = 0.0;
-    if (h < m) {
-      double t = 0.0;
-      for (int q = 0; q < m; ++q) t += Ms[h * m + q] * xrow[q];
-      u0 = t;
-      part += pr[h] * t;
-    }
-    if (h + 32 < m) {
-      double t = 0.0;
-      for (int q = 0; q < m; ++q) t += Ms[(h + 32) * m + q] * xrow[q];
-      u1 = t;
-      part += pr[h + 32] * t;
+    double part = 0.0;
+#pragma unroll 1
+    for (int row = h; row < m; row += 32) {
+      const double u = dot8(MT + row, m, xrow, m);
+      ush[row] = u;
+      part = fma((double)pr[row], u, part);
     }
     for (int o = 16; o >= 1; o >>= 1) part += __shfl_xor(part, o);
     const double rsp = 1.0 + delta * part;
     const double ratio = lane_read(rsp, 0) * lane_read(rsp, 32);
     if (usb[r] < fabs(ratio)) {
-      if (h < m) {
-        double t = 0.0;
-        for (int q = 0; q < m; ++q) t += pr[q] * Ms[q * m + h];
-        wsh[h] = t;
-      }
-      if (h + 32 < m) {
-        double t = 0.0;
-        for (int q = 0; q < m; ++q) t += pr[q] * Ms[q * m + h + 32];
-        wsh[h + 32] = t;
-      }
+#pragma unroll 1
+      for (int col = h; col < m; col += 32) wsh[col] = dot8(M + col, m, pr, m);
       wave_fence();
       const double c = delta / rsp;
-      if (h < m) {
-        const double cu = c * u0;
-        for (int b = 0; b < m; ++b) Ms[h * m + b] -= cu * wsh[b];
-      }
-      if (h + 32 < m) {
-        const double cu = c * u1;
-        for (int b = 0; b < m; ++b) Ms[(h + 32) * m + b] -= cu * wsh[b];
+      // element (a, b) of M and (b, a) of MT both take fma(-(c u_a), w_b, .)
+#pragma unroll 1
+      for (int h2 = h; h2 < m; h2 += 32) {
+        axpy8(MT + h2, m, c * ush[h2], nullptr, wsh, 0.0, m);
+        axpy8(M + h2, m, c, ush, nullptr, wsh[h2], m);
       }
       mask |= 1u << r;
       acc_ratio(acc, fabs(ratio));
@@ -901,6 +956,19 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
   const int nch = (N + S - 1) / S;
   double M[2 * TT][TT];
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
+  if constexpr (T == 0) {
+    // column-major copies of the inverses for the chain (A, B are free here)
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int m = w.ne[s2];
+      const double *Ms = s2 ? L.Ms1 : L.Ms0;
+      double *MT = s2 ? L.B : L.A;
+      for (int t = TID; t < m * m; t += kThreads) {
+        const int a = t / m, b = t - (t / m) * m;
+        MT[b * m + a] = Ms[t];
+      }
+    }
+    SYNC();
+  }
   if constexpr (T > 0) {
     if (TID < 64) {
       const int m = w.ne[sp];
@@ -1202,6 +1270,7 @@ __global__ void __launch_bounds__(kThreads) k_init(const WalkerDesc *__restrict_
 __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *__restrict__ descs, LdsPlan pl, int set_tracked) {
   const WalkerDesc &w = descs[blockIdx.x];
   Lds L = carve(pl);
+  bind_mats(L, w, pl, 0);
   load_bonds(w, L, pl.bond_words);
   double la = 0.0;
   int sg = 1;
@@ -1237,6 +1306,7 @@ template <typename F>
 __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   Lds L = carve(pl);
+  bind_mats(L, w, pl, blockIdx.x & 1);
   load_bonds(w, L, pl.bond_words);
   const int N = w.N;
   {
@@ -1357,6 +1427,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
   const WalkerDesc &w = descs[blockIdx.x];
   const long long t0 = wall_clock64();
   Lds L = carve(pl);
+  bind_mats(L, w, pl, 0);
   L.S = w.chunk;
   load_bonds(w, L, pl.bond_words);
   if constexpr (TSEL >= 0) {
@@ -1383,11 +1454,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int meas_slots(const WalkerDesc &w) { return w.nblk > 1 ? w.nblk - 1 : 1; }
 
-__global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *__restrict__ descs, LdsPlan pl, int slots) {
-  const WalkerDesc &w = descs[blockIdx.x / slots];
-  const int q = blockIdx.x % slots;
-  if (q >= meas_slots(w)) return;
-  Lds L = carve(pl);
+__device__ __forceinline__ void measure_boundary(const WalkerDesc &w, Lds &L, int q) {
   const int N = w.N;
   const size_t rec = (size_t)w.nobs + 1;
   double *part = w.mpart + (size_t)q * rec;
@@ -1444,6 +1511,17 @@ __global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *__restri
   const double *Msp[2] = {L.Ms0, L.Ms1};
   measure_point(w, PR, XL, Msp, sg, L, part, ms);
   if (TID == 0) part[w.nobs] = wrap;
+  SYNC();
+}
+
+// slots: workgroups per walker; each takes boundaries q, q + slots, ...
+// (one workgroup per walker when the Ne x Ne work matrices are in device
+// memory, since they are one per walker)
+__global__ void __launch_bounds__(kThreads) k_measure(const WalkerDesc *__restrict__ descs, LdsPlan pl, int slots) {
+  const WalkerDesc &w = descs[blockIdx.x / slots];
+  Lds L = carve(pl);
+  bind_mats(L, w, pl, 0);
+  for (int q = blockIdx.x % slots; q < meas_slots(w); q += slots) measure_boundary(w, L, q);
 }
 
 __global__ void __launch_bounds__(kThreads) k_measure_sum(const WalkerDesc *__restrict__ descs) {
@@ -1528,8 +1606,9 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
   double *const fv = w.fv + (size_t)sp * n * mm;
   double *const frho = w.frho + (size_t)sp * n;
   double *H = L.Ms0, *Mp = L.Ms1, *Mred = L.A;
-  double *y = L.vec, *z = L.vec + 64, *vsum = L.vec + 128, *acol = L.vec + 192, *brow = L.vec + 256,
-         *tv = L.vec + 320;
+  const int vs = L.vs;
+  double *y = L.vec, *z = L.vec + vs, *vsum = L.vec + 2 * vs, *acol = L.vec + 3 * vs, *brow = L.vec + 4 * vs,
+         *tv = L.vec + 5 * vs;
   // scal[20] log_rne, [21] sign_rne, [22] zero flag, [23] log_rho
   if (TID == 0) { L.scal[20] = 0.0; L.scal[21] = 1.0; L.scal[22] = 0.0; L.scal[23] = 0.0; }
   SYNC();
@@ -1653,7 +1732,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         }
       }
       const double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
-      for (int a = TID; a < 64; a += kThreads) vsum[a] = 0.0;
+      for (int a = TID; a < vs; a += kThreads) vsum[a] = 0.0;
       SYNC();
       for (int pass = 0; pass < 2 && m > 0; ++pass) {
         if (qcache) {
@@ -1873,6 +1952,7 @@ __global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *__restrict_
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   const int sp = blockIdx.x & 1;
   Lds L = carve(pl);
+  bind_mats(L, w, pl, sp);
   load_bonds(w, L, pl.bond_words);
   // column storage: LDS when the plan holds N entries of F, else device memory
   F *fw = (L.phi && (size_t)pl.phi_elems * sizeof(double) >= (size_t)w.N * sizeof(F))
@@ -1924,7 +2004,9 @@ __device__ void left_state(const WalkerDesc &w, int sp, int b, Lds &L) {
 
 __global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *__restrict__ descs, int mm, int b, int sp, double *G) {
   const WalkerDesc &w = descs[0];
-  Lds L = carve(mm, 0);
+  const LdsPlan pl = parity_plan(mm);
+  Lds L = carve(pl);
+  bind_mats(L, w, pl, 0);
   const int N = w.N, m = w.ne[sp];
   right_state(w, sp, b, L);
   left_state(w, sp, b, L);
@@ -1950,7 +2032,9 @@ __global__ void __launch_bounds__(kThreads) k_green(const WalkerDesc *__restrict
 
 __global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *__restrict__ descs, int mm, int slice, int site) {
   const WalkerDesc &w = descs[0];
-  Lds L = carve(mm, 0);
+  const LdsPlan pl = parity_plan(mm);
+  Lds L = carve(pl);
+  bind_mats(L, w, pl, 0);
   const int N = w.N, l = slice + 1;
   double r = 1.0;
   for (int sp = 0; sp < 2; ++sp) {
@@ -1980,7 +2064,9 @@ __global__ void __launch_bounds__(kThreads) k_flip_ratio(const WalkerDesc *__res
 
 __global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *__restrict__ descs, int mm, int sp, int k, int j) {
   const WalkerDesc &w = descs[0];
-  Lds L = carve(mm, 0);
+  const LdsPlan pl = parity_plan(mm);
+  Lds L = carve(pl);
+  bind_mats(L, w, pl, 0);
   for (int s2 = 0; s2 < 2; ++s2) {
     right_stack(w, s2, L, w.PhiR[s2]);
     double la;
@@ -2085,21 +2171,21 @@ hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStre
 }
 hipError_t launch_green(const WalkerDesc *d, int mm, int b, int sp, double *G, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0});
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0});
   lds_attr(k_green, by);
   hipLaunchKernelGGL(k_green, dim3(1), dim3(kThreads), by, st, d, mm, b, sp, G);
   return hipGetLastError();
 }
 hipError_t launch_flip_ratio(const WalkerDesc *d, int mm, int slice, int site, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0});
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0});
   lds_attr(k_flip_ratio, by);
   hipLaunchKernelGGL(k_flip_ratio, dim3(1), dim3(kThreads), by, st, d, mm, slice, site);
   return hipGetLastError();
 }
 hipError_t launch_swap_ratio(const WalkerDesc *d, int mm, int sp, int k, int j, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0});
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0});
   lds_attr(k_swap_ratio, by);
   hipLaunchKernelGGL(k_swap_ratio, dim3(1), dim3(kThreads), by, st, d, mm, sp, k, j);
   return hipGetLastError();

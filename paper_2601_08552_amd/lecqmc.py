@@ -22,7 +22,7 @@ FP64 = 0
 MIXED = 1
 NO_FOCK = 1
 NO_FLIPS = 2
-MAX_NE = 64
+MAX_NE = 256
 
 EXPORTED = [
     "lecqmc_ctx_create", "lecqmc_ctx_destroy", "lecqmc_ctx_synchronize", "lecqmc_ctx_bytes_in_use",

@@ -51,6 +51,9 @@ CASES = {
     # 16 < Ne <= 32 (widest register tile) and Ne > 32 (inverse kept in LDS)
     "square6_ne20": (lambda: W.square_lattice(6), dict(U=4.0, beta=0.6, dtau=0.1, n_stab=3, n_up=20, n_dn=17)),
     "chain40_ne34": (lambda: W.periodic_chain(40), dict(U=2.0, beta=0.4, dtau=0.1, n_stab=2, n_up=34, n_dn=5)),
+    # Ne > 64: the Ne x Ne work matrices move from LDS to device memory
+    "square12_ne80": (lambda: W.square_lattice(12), dict(U=4.0, beta=0.4, dtau=0.1, n_stab=2, n_up=80, n_dn=70)),
+    "flat48_ne72": (lambda: W.flat_band_chain(48), dict(U=2.0, beta=0.5, dtau=0.05, n_stab=4, n_up=72, n_dn=24)),
 }
 
 
@@ -89,7 +92,7 @@ def test_log_weight(lq, ctx, name):
 
 
 @pytest.mark.parametrize("name", ["square4_u4", "pchain6_ragged", "flat4", "square6_ne5", "square4_empty_dn",
-                                  "chain4_full_up", "square8_ne12", "square6_ne20", "chain40_ne34"])
+                                  "chain4_full_up", "square8_ne12", "square6_ne20", "chain40_ne34", "flat48_ne72"])
 def test_green(lq, ctx, name):
     lat, par, g, o = _pair(lq, ctx, name)
     for b in sorted({0, 1, par.n_stab, min(par.n_stab + 3, par.L_tau), par.L_tau}):
@@ -99,7 +102,8 @@ def test_green(lq, ctx, name):
 
 
 @pytest.mark.parametrize("name", ["square4_u4", "pchain6_ragged", "chain5_open", "flat4", "square6_ne5",
-                                  "square4_empty_dn", "square8_ne12", "square6_ne20", "chain40_ne34"])
+                                  "square4_empty_dn", "square8_ne12", "square6_ne20", "chain40_ne34",
+                                  "square12_ne80", "flat48_ne72"])
 def test_flip_ratio(lq, ctx, name):
     lat, par, g, o = _pair(lq, ctx, name)
     rng = np.random.default_rng(7)
@@ -110,7 +114,7 @@ def test_flip_ratio(lq, ctx, name):
 
 
 @pytest.mark.parametrize("name", ["square4_u4", "pchain6_ragged", "chain5_open", "flat4", "square6_ne5",
-                                  "square4_one_each", "square8_ne12"])
+                                  "square4_one_each", "square8_ne12", "square12_ne80", "flat48_ne72"])
 def test_swap_ratio(lq, ctx, name):
     lat, par, g, o = _pair(lq, ctx, name)
     _, ou, od, _ = o.state()

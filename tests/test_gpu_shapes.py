@@ -183,3 +183,27 @@ def test_mixed_shape_batch_equals_alone(lq):
         assert a.stats()["logw_drift"] == b.stats()["logw_drift"]
     bt.close()
     ctx.close()
+
+
+def test_large_ne_in_a_batch(lq):
+    """A walker with Ne > 64 (work matrices in device memory for the whole
+    launch) batched with walkers that alone keep them in LDS: every walker
+    matches itself swept alone, and the large one matches the oracle."""
+    specs = [(3, 2, 6), (40, 12, 8), (90, 66, 12)]
+    ctx = lq.Context(0)
+    alone, batch, cfg = [], [], []
+    for (nu, nd, Ls) in specs:
+        lat, par = _case(nu, nd, Ls=Ls, beta=0.5, seed=50 + nu)
+        cfg.append((lat, par))
+        alone.append(lq.Walker(ctx, lat, par))
+        batch.append(lq.Walker(ctx, lat, par))
+    for a in alone:
+        a.sweep(2, measure=True)
+    lq.sweep_batch(batch, 2, measure=True)
+    for a, b in zip(alone, batch):
+        assert _same(a, b)
+    lat, par = cfg[-1]
+    o = oracle.Walker(lat, par)
+    o.sweep(2, measure=True)
+    _matches_oracle(batch[-1], o)
+    ctx.close()
