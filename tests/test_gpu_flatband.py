@@ -1,0 +1,72 @@
+"""The flat-band workload at full size: the cross-stitch chain of 256 cells
+(N = 512 sites, five bond colours), U = 2, the flat band half filled
+(N_up + N_dn = 256), beta = 10, dtau = 0.05 (200 slices), a QR every 10
+slices.  With Ne = 128 per spin and above, the Ne x Ne work matrices live in
+device memory.  At zero imbalance one whole sweep must follow the oracle's
+chain; at the largest imbalance (Ne = 256 and 0) the weight and sampled flip
+and swap ratios must match it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_08552_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lq():
+    from paper_2601_08552_amd import lecqmc
+    lecqmc.load()
+    return lecqmc
+
+
+def _close(a, b, rtol=RTOL):
+    return abs(a - b) <= rtol * max(1.0, abs(b))
+
+
+def test_flat_band_half_filled_sweep(lq):
+    lat, par = W.config_flat_band(256, imbalance=0, beta=10.0)
+    assert (lat.n_sites, par.n_up, par.n_dn, par.L_tau) == (512, 128, 128, 200)
+    ctx = lq.Context(0)
+    g = lq.Walker(ctx, lat, par)
+    o = oracle.Walker(lat, par)
+    lg, sg = g.log_weight()
+    lo, so = o.log_weight()
+    assert sg == so and _close(lg, lo)
+    print("sweeping", flush=True)
+    g.sweep(1)
+    o.sweep(1)
+    fg, ug, dg, _ = g.state()
+    fo, uo, do, _ = o.state()
+    assert np.array_equal(ug, uo) and np.array_equal(dg, do)
+    assert np.array_equal(fg, fo)
+    lg, sgg = g.tracked_weight()
+    lo, soo = o.tracked_weight()
+    assert sgg == soo and _close(lg, lo)
+    stg, sto = g.stats(), o.stats()
+    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts"):
+        assert stg[k] == sto[k], k
+    assert stg["logw_drift"] < 1e-8
+    ctx.close()
+
+
+def test_flat_band_full_imbalance_ratios(lq):
+    lat, par = W.config_flat_band(256, imbalance=256, beta=10.0)
+    assert (par.n_up, par.n_dn) == (256, 0)
+    ctx = lq.Context(0)
+    g = lq.Walker(ctx, lat, par)
+    o = oracle.Walker(lat, par)
+    lg, sg = g.log_weight()
+    lo, so = o.log_weight()
+    assert sg == so and _close(lg, lo)
+    for (l, i) in ((0, 0), (101, 333)):
+        assert _close(g.flip_ratio(l, i), o.flip_ratio(l, i))
+    _, ou, _, _ = o.state()
+    empty = [s for s in range(lat.n_sites) if s not in set(ou.tolist())]
+    for (k, j) in ((0, empty[0]), (255, empty[-1])):
+        assert _close(g.swap_ratio(0, k, j), o.swap_ratio(0, k, j))
+    ctx.close()
