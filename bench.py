@@ -91,6 +91,11 @@ def cpu_baseline(procs, sweeps):
             "sec_per_sweep_per_core": float(np.median(times) / sweeps)}
 
 
+def note(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +106,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default flip-chain shapes")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256-walker uneven batch")
+    ap.add_argument("--no-flat", action="store_true", help="skip the 128-walker flat-band batch")
     ap.add_argument("--cpu-procs", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=10)
     args = ap.parse_args()
@@ -119,16 +125,19 @@ def main():
 
     def run(precision):
         """Timed batched sweeps of the workload at one precision."""
+        note(f"dilute workload, precision {precision}: creating {args.walkers} walkers")
         walkers = []
         for s in range(args.walkers):
             lat, par = W.config_dilute(seed=s + 1, walker_id=s, precision=precision)
             walkers.append(lecqmc.Walker(ctx, lat, par))
+        note("autotuning")
         t_tune = time.perf_counter()
         tuned = lecqmc.autotune(walkers) if not args.no_autotune else None
         t_tune = time.perf_counter() - t_tune
         for _ in range(args.warmup):
             lecqmc.sweep_batch(walkers, 1)
         ctx.synchronize()
+        note("timing")
         ctx.set_timing(True)
         ctx.phase_times()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -157,13 +166,16 @@ def main():
     def run_uneven():
         """The batched uneven-walker workload: 256 chains of mixed lattice size,
         Ne and beta, autotuned, one fixed batch, each sweep a HIP graph replay."""
+        note("uneven batch: creating 256 walkers")
         cfg = W.config_batched(256)
         gs = torch.cuda.Stream()
         gctx = lecqmc.Context(0, stream=gs)
         ws = [lecqmc.Walker(gctx, lat, par) for lat, par in cfg]
+        note("uneven batch: autotuning")
         t_tune = time.perf_counter()
         res = lecqmc.autotune(ws)
         t_tune = time.perf_counter() - t_tune
+        note("uneven batch: timing")
         batch = lecqmc.Batch(ws)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=gs):
@@ -195,6 +207,41 @@ def main():
                          "beta in {8,16}, dtau=0.05, QR every 10 slices, FP64; sweeps replayed from a HIP graph"}
         batch.close()
         gctx.close()
+        return out
+
+    def run_flat():
+        """The flat-band workload: 128 walkers of the 256-cell chain (512
+        sites), flat band half filled with no imbalance (128 + 128), beta = 10,
+        autotuned, one batched sweep timed after a warm-up sweep."""
+        lat, par = W.config_flat_band(256, imbalance=0, beta=10.0)
+        fctx = lecqmc.Context(0, stream=stream)
+        mk = lambda s: lecqmc.Walker(fctx, lat, W.Params(**{**par.__dict__, "seed": s + 1, "walker_id": s}))
+        # every walker has the same shape key: tune on eight, the context
+        # hands the choice to the walkers created after
+        note("flat band: autotuning on 8 walkers")
+        ws = [mk(s) for s in range(8)]
+        t_tune = time.perf_counter()
+        res = lecqmc.autotune(ws)
+        t_tune = time.perf_counter() - t_tune
+        note(f"flat band: creating 120 more walkers (shape {res[0][:2]})")
+        ws += [mk(s) for s in range(8, 128)]
+        note("flat band: warm-up sweep")
+        lecqmc.sweep_batch(ws, 1)
+        fctx.synchronize()
+        note("flat band: timed sweep")
+        t0 = time.perf_counter()
+        lecqmc.sweep_batch(ws, 1)
+        fctx.synchronize()
+        wall = time.perf_counter() - t0
+        upd = len(ws) * lat.n_sites * par.L_tau
+        out = {"value": upd / wall, "unit": "HS-field updates/s", "walkers": len(ws), "steps": 1,
+               "ms_per_step": wall * 1e3, "hbm_gib": fctx.bytes_in_use() / 2**30, "autotune_s": t_tune,
+               "chain_shape": {"tile": ws[-1].shape[0], "chunk": ws[-1].shape[1]},
+               "config": "flat-band chain, 256 cells (N=512), t=t'=1, U=2, 128+128 particles, beta=10, "
+                         "dtau=0.05 (200 slices), QR every 10 slices, FP64"}
+        for w in ws:
+            w.close()
+        fctx.close()
         return out
 
     r64 = run(lecqmc.FP64)
@@ -259,7 +306,10 @@ def main():
         }
     if not args.no_uneven:
         out["uneven_batch"] = run_uneven()
+    if not args.no_flat:
+        out["flat_band"] = run_flat()
     if not args.no_cpu_baseline:
+        note("cpu baseline (the oracle on the host cores)")
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(procs, args.cpu_sweeps)
     print(json.dumps(out), flush=True)

@@ -81,22 +81,30 @@ struct lecqmc_walker {
 extern "C" const char *lecqmc_last_error(void) { return g_err; }
 
 // Flip-chain shape of a walker: the register tile T (the Ne x Ne inverse in
-// registers for Ne <= 8T, or T = 0: in LDS) and the sites per staged chunk.
-// Defaults by Ne, measured on the dilute workload; lecqmc_autotune replaces
-// them by timed choices.  Every shape computes the same chain; the tile
-// changes the order of the ratio's partial sums (rounding only), the chunk
-// changes nothing.
+// registers for Ne <= 8T), T = 0 (the inverse in memory, site by site) or
+// kDelayed (the delayed chunk update), and the sites per staged chunk.
+// Defaults by Ne, from measurements of the forward pass; lecqmc_autotune
+// replaces them by timed choices.  Every shape samples the same chain; the
+// shape changes only the rounding of the ratios.
+static bool shape_valid(int mmax, int tile, int chunk);
 static void shape_default(int mmax, int *tile, int *chunk) {
-  *tile = mmax <= 8 ? 1 : mmax <= 16 ? 2 : mmax <= 32 ? 4 : 0;
-  *chunk = mmax <= 16 ? 32 : mmax <= 32 ? 16 : 4;
+  *tile = mmax <= 8 ? 1 : mmax <= 16 ? 2 : mmax <= 32 ? 4 : kDelayed;
+  *chunk = mmax <= 16 ? 32 : mmax <= 32 ? 16 : 8;
+  if (*tile == kDelayed && !shape_valid(mmax, *tile, *chunk)) *chunk = 4;
 }
-static int shape_xld(int mmax, int tile) { return tile > 0 ? 8 * tile : mmax; }
+// row stride of the staged chunk rows: 8T for a register tile; Ne, or the
+// next odd number for the delayed chain (its threads read rows side by side)
+static int shape_xld(int mmax, int tile) {
+  return tile == kDelayed ? (mmax | 1) : tile > 0 ? 8 * tile : mmax;
+}
 static bool shape_valid(int mmax, int tile, int chunk) {
-  if (!(tile == 0 || tile == 1 || tile == 2 || tile == 4)) return false;
-  if (tile > 0 && mmax > 8 * tile) return false;
+  if (!(tile == 0 || tile == 1 || tile == 2 || tile == 4 || tile == kDelayed)) return false;
+  if (tile > 0 && tile != kDelayed && mmax > 8 * tile) return false;
   if (!(chunk == 4 || chunk == 8 || chunk == 16 || chunk == 32)) return false;
+  if (tile == kDelayed && chunk > 16) return false;   // the delayed chain's registers hold 16 sites
   // both staging buffers (streamed walker) must fit next to the fixed layout
-  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, mmax > kLdsNe ? 1 : 0};
+  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, mmax > kLdsNe ? 1 : 0,
+                  tile == kDelayed ? 4 * kDS * kDS : 0};
   return lds_bytes(p) <= kLdsLimit;
 }
 static void shape_apply(WalkerDesc &h, int tile, int chunk) {
@@ -143,7 +151,7 @@ static LdsPlan plan_for(LdsPlan p, const std::vector<long> &needs, int bond_need
 // Walkers of one launch share a precision (the sweep launchers group them).
 // Resident blocks are counted in doubles: FP32 storage needs half of them.
 static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
-  int mm = 1, bonds = 0, slots = 1, xs = 0, smax = 0, tile = n > 0 ? ws[0]->h.tile : 0;
+  int mm = 1, bonds = 0, slots = 1, xs = 0, smax = 0, tile = n > 0 ? ws[0]->h.tile : 0, dgn = 0;
   std::vector<long> fwd, left, fock, fresh;
   bool compact = true;
   const int mixed = n > 0 ? ws[0]->h.mixed : 0;
@@ -161,11 +169,12 @@ static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
     bonds = std::max(bonds, w->h.bond_words);
     slots = std::max(slots, w->nblk - 1);
     if (w->h.tile != tile) tile = -1;
+    if (w->h.tile == kDelayed) dgn = 4 * kDS * kDS;
   }
   if (!compact) bonds = 0;
   const int gm = mm > kLdsNe ? 1 : 0;
   if (gm) slots = 1;   // one estimator workgroup per walker: the work matrices are one per walker
-  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm}, fbase{mm, 0, 0, 0, xs, smax, gm};
+  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm, 0}, fbase{mm, 0, 0, 0, xs, smax, gm, dgn};
   return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(base, fock, bonds, false),
           base,                              plan_for(base, fresh, bonds, false), slots,
           mixed,                             tile};
@@ -221,7 +230,7 @@ struct Plan {
   size_t off_sc, off_desc, off_s, off_occ[2], off_LS[2], off_LX[2], off_RQ[2], off_RV[2], off_Minv[2], off_PhiR[2], off_X[2],
       off_T[2], off_Aw[2], off_mpart, off_mscr, off_fq, off_fw, off_fVp, off_fgc, off_fgs, off_fv, off_frho, off_fmark, off_obs,
       off_dbg, off_col, off_bi, off_bj, off_bdiag, off_boff, off_bh, off_epsf, off_eps, off_sub, off_bij, off_bci,
-      off_coef, off_bigm;
+      off_coef, off_bigm, off_dch;
   size_t mscr_stride;
   size_t total;
 };
@@ -287,6 +296,7 @@ static Plan make_plan(int N, int L, int nstab, int ne0, int ne1, int nbonds, int
   p.off_bci = take(nbonds);
   p.off_coef = take(sizeof(double) * 2 * kMaxCoef);
   p.off_bigm = take(sizeof(double) * 8 * (size_t)mmax * mmax);
+  p.off_dch = take(sizeof(double) * (8 * (size_t)mmax * kDS + 4 * kDS * kDS));
   p.total = o;
   return p;
 }
@@ -476,6 +486,7 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   d.obs = (double *)(base + p.off_obs);
   d.dbg = (double *)(base + p.off_dbg);
   d.bigm = (double *)(base + p.off_bigm);
+  d.dch = (double *)(base + p.off_dch);
   int *col_start = (int *)(base + p.off_col);
   int *bi = (int *)(base + p.off_bi);
   int *bj = (int *)(base + p.off_bj);
@@ -765,7 +776,7 @@ extern "C" int lecqmc_set_shape(lecqmc_walker *w, int32_t tile, int32_t chunk) {
 // walker's device state is rebuilt by the next sweep), timed per walker by
 // the kernel's own wall clock.  The state is restored afterwards, so tuning
 // leaves the Markov chains where they were.
-constexpr int kTiles = 4;
+constexpr int kTiles = 5;
 extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *tile_out, int32_t *chunk_out,
                                double *fwd_ms_out) {
   if (!ws || n <= 0) return fail(LECQMC_EINVAL, "bad arguments");
@@ -826,7 +837,7 @@ extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *til
     if (e == hipSuccess)
       e = hipMemcpyAsync(snap + off[t] + align256(nf), ws[t]->h.sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st);
   }
-  static const int tiles[kTiles] = {1, 2, 4, 0}, chunks[4] = {4, 8, 16, 32};
+  static const int tiles[kTiles] = {1, 2, 4, 0, kDelayed}, chunks[4] = {4, 8, 16, 32};
   for (int ti = 0; ti < kTiles && e == hipSuccess; ++ti)
     for (int ci = 0; ci < 4 && e == hipSuccess; ++ci)
       for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {

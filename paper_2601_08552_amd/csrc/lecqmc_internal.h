@@ -9,6 +9,8 @@ namespace lecqmc {
 constexpr int kThreads = 256;   // one workgroup (4 wave64) per walker
 constexpr int kMaxNe = 256;     // particles per spin
 constexpr int kLdsNe = 64;      // largest Ne whose Ne x Ne work matrices are kept in LDS
+constexpr int kDelayed = 9;     // chain shape code of the delayed (submatrix) flip update
+constexpr int kDS = 32;         // sites per chunk at most (accepted-site masks are 32 bits)
 
 // counter-based generator streams (shared layout with the walker's key)
 enum Stream : uint32_t { kFlip = 1, kSwapK = 2, kSwapJ = 3, kSwapAcc = 4, kInitField = 5, kInitOcc = 6 };
@@ -83,6 +85,8 @@ struct WalkerDesc {
   int *fmark;                   // [2][N] occupancy marks / permutation scratch
   double *obs;                  // [nobs]
   double *dbg;                  // [N*N] parity-surface output (N <= dbg_n) else [8]
+  double *dch;                  // delayed flip chain: [2 spins][U, W, U~, W~: mmax x kDS each] +
+                                // [2 (row, column)][2 spins][kDS][kDS] records
   double *bigm;                 // [2 slots][4][mmax^2] the Ne x Ne work matrices of a launch whose
                                 // largest Ne exceeds kLdsNe (slot = spin in per-spin kernels)
   Scalars *sc;
@@ -99,6 +103,7 @@ struct WalkerDesc {
 struct LdsPlan {
   int mm, phi_elems, stage_ps, bond_words, xs_elems, smax;
   int gm;   // 1: the Ne x Ne work matrices live in each walker's bigm, not in LDS
+  int dgn;  // LDS doubles for the delayed chain's chunk and coefficient matrices (4 kDS^2, or 0)
 };
 // LDS doubles that a walker's resident blocks of `entries` elements need
 __host__ __device__ inline long phi_doubles(long entries, int elem_bytes) {

@@ -14,6 +14,8 @@
 // QR update for particle removal / addition (SM Sec. I.A and I.B).
 #include <math.h>
 
+#include <type_traits>
+
 #include "lecqmc_internal.h"
 
 namespace lecqmc {
@@ -65,6 +67,7 @@ struct Lds {
   double *us;     // [2 buf][S]              staged uniforms
   double *dl;     // [2 buf][2 spin][S]      staged flip factors Delta
   int8_t *fs;     // [2 buf][S]              staged Ising fields
+  double *dg;     // delayed chain: [2 spin][kDS][kDS] chunk matrices, then as many coefficients, or nullptr
   double *phi;    // resident Slater blocks, or nullptr
   double *bonds;  // compact bond tables (coef | bij | bci), or nullptr
   int S;          // sites per staged chunk
@@ -77,7 +80,7 @@ __host__ __device__ inline int vec_len(int mm) { return mm > 64 ? mm : 64; }
 __host__ __device__ inline size_t lds_doubles_fixed(const LdsPlan &p) {
   const size_t mm = p.mm < 1 ? 1 : p.mm, S = p.smax > 0 ? p.smax : 0, vs = vec_len((int)mm);
   return 256 + 64 + (p.gm ? 0 : 4 * mm * mm) + 8 * vs + 4 * vs + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S +
-         4 * S + (2 * S + 7) / 8;
+         4 * S + (2 * S + 7) / 8 + (size_t)p.dgn;
 }
 
 size_t lds_bytes(const LdsPlan &p) {
@@ -87,7 +90,7 @@ size_t lds_bytes(const LdsPlan &p) {
 
 extern __shared__ double lds_raw[];
 
-__device__ Lds carve(const LdsPlan &pl) {
+__device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   const int mm = pl.mm < 1 ? 1 : pl.mm;
   const int S = pl.smax > 0 ? pl.smax : 0;
   Lds L;
@@ -111,6 +114,7 @@ __device__ Lds carve(const LdsPlan &pl) {
   L.us = p; p += 2 * S;
   L.dl = p; p += 4 * S;
   L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
+  L.dg = pl.dgn > 0 ? p : nullptr; p += pl.dgn;
   L.phi = pl.phi_elems > 0 ? p : nullptr; p += pl.phi_elems;
   L.bonds = pl.bond_words > 0 ? p : nullptr; p += (pl.bond_words + 1) / 2;
   L.iscal = reinterpret_cast<int *>(p);
@@ -131,7 +135,7 @@ __device__ __forceinline__ void bind_mats(Lds &L, const WalkerDesc &w, const Lds
   L.A = base + 2 * q;
   L.B = base + 3 * q;
 }
-__device__ __forceinline__ LdsPlan parity_plan(int mm) { return LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0}; }
+__device__ __forceinline__ LdsPlan parity_plan(int mm) { return LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0, 0}; }
 
 #define TID (static_cast<int>(threadIdx.x))
 #define SYNC() __syncthreads()
@@ -869,6 +873,257 @@ __device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *x
   return mask;
 }
 
+// ---------------------------------------------------------------------------
+// Delayed (submatrix) flip chain, for any Ne.  Per staged chunk of cnt sites
+// and per spin, with x_r the left rows, p_r the right rows and M = M^{-1}:
+//   U = M X (Ne x cnt),  W = P M (cnt x Ne),  G = P U (cnt x cnt)
+// (all waves).  Wave 0 then decides the sites in order on G alone: site r
+// has a_r = G[r][r], and an accepted site moves the rest of the chunk by
+// G <- G - c_r G[:, r] G[r, :] (the Sherman-Morrison term seen through P and
+// X).  Finally (all waves) the inverse takes the k accepted terms at once:
+//   u~_t = U[:, r_t] - sum_{t'<t} c_t' G_t'[r_t', r_t] u~_t',
+//   w~_t = W[r_t, :] - sum_{t'<t} c_t' G_t'[r_t, r_t'] w~_t',
+//   M <- M - sum_t c_t u~_t w~_t^T,
+// which is the sequence of rank-1 updates of the site-by-site chain with M
+// read three times per chunk instead of per site.  G_t' is G when site r_t'
+// was accepted; its row and column r_t' are recorded then.
+// ---------------------------------------------------------------------------
+struct DelayedBufs {
+  double *U, *W, *Ut, *Wt, *rrec, *crec;
+};
+__device__ __forceinline__ DelayedBufs dbufs(const WalkerDesc &w, int sp) {
+  const size_t mb = (size_t)w.mmax * kDS;
+  double *base = w.dch + (size_t)sp * 4 * mb;
+  double *rec = w.dch + 8 * mb;
+  return DelayedBufs{base, base + mb, base + 2 * mb, base + 3 * mb, rec + (size_t)sp * kDS * kDS,
+                     rec + (size_t)(2 + sp) * kDS * kDS};
+}
+
+// U, W, then G into LDS (all threads); ends with a barrier.  KS >= cnt.
+// A thread takes one row a of U (all sites at once: each block of eight
+// entries of M row a serves every site) or one column b of W (likewise with
+// M column b, read side by side across threads).
+template <int KS, typename PE>
+__device__ __forceinline__ void delayed_prologue(const WalkerDesc &w, Lds &L, const double *xsb, int xld, const PE *const prow[2],
+                                 const int ldp[2], int cnt, int S) {
+  const int m0 = w.ne[0], m1 = w.ne[1];
+  for (int e = TID; e < 2 * (m0 + m1); e += kThreads) {
+    const bool isw = e >= m0 + m1;
+    const int f = isw ? e - (m0 + m1) : e;
+    const int sp = f < m0 ? 0 : 1, idx = f < m0 ? f : f - m0, m = sp ? m1 : m0;
+    const double *M = sp ? L.Ms1 : L.Ms0;
+    const DelayedBufs B = dbufs(w, sp);
+    double acc[KS];
+#pragma unroll
+    for (int r = 0; r < KS; ++r) acc[r] = 0.0;
+    if (!isw) {
+      // U[a][r] = sum_b M[a][b] X[r][b]
+      const double *Mr = M + (size_t)idx * m;
+      const double *X = xsb + (size_t)sp * S * xld;
+      int b0 = 0;
+      double mn[8];
+      if (m >= 8)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mn[q] = Mr[q];
+      for (; b0 + 8 <= m; b0 += 8) {
+        double mv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mv[q] = mn[q];
+        if (b0 + 16 <= m)   // the next block's loads go out before this block's arithmetic
+#pragma unroll
+          for (int q = 0; q < 8; ++q) mn[q] = Mr[b0 + 8 + q];
+#pragma unroll
+        for (int r = 0; r < KS; ++r)
+          if (r < cnt)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[r] = fma(mv[q], X[r * xld + b0 + q], acc[r]);
+      }
+      for (; b0 < m; ++b0) {
+        const double mv = Mr[b0];
+#pragma unroll
+        for (int r = 0; r < KS; ++r)
+          if (r < cnt) acc[r] = fma(mv, X[r * xld + b0], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < KS; ++r)
+        if (r < cnt) B.U[idx * kDS + r] = acc[r];
+    } else {
+      // W[r][b] = sum_a P[r][a] M[a][b]
+      const PE *P = prow[sp];
+      const int lp = ldp[sp];
+      int a0 = 0;
+      double mn[8];
+      if (m >= 8)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mn[q] = M[(size_t)q * m + idx];
+      for (; a0 + 8 <= m; a0 += 8) {
+        double mv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mv[q] = mn[q];
+        if (a0 + 16 <= m)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) mn[q] = M[(size_t)(a0 + 8 + q) * m + idx];
+#pragma unroll
+        for (int r = 0; r < KS; ++r)
+          if (r < cnt)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[r] = fma((double)P[r * lp + a0 + q], mv[q], acc[r]);
+      }
+      for (; a0 < m; ++a0) {
+        const double mv = M[(size_t)a0 * m + idx];
+#pragma unroll
+        for (int r = 0; r < KS; ++r)
+          if (r < cnt) acc[r] = fma((double)P[r * lp + a0], mv, acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < KS; ++r)
+        if (r < cnt) B.W[r * w.mmax + idx] = acc[r];
+    }
+  }
+  SYNC();
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    const PE *P = prow[sp];
+    const int lp = ldp[sp];
+    const DelayedBufs B = dbufs(w, sp);
+    double *G = L.dg + sp * kDS * kDS;
+    for (int e = TID; e < cnt * cnt; e += kThreads) {
+      const int r = e / cnt, s2 = e - r * cnt;
+      G[r * kDS + s2] = dot8(B.U + s2, kDS, P + r * lp, m);
+    }
+  }
+  SYNC();
+}
+
+// The sequential decisions on G (wave 0; lanes 0..31 spin up, 32..63 spin
+// down, lane j holding column j of its spin's G).  Records c_t and the
+// accepted sites for the epilogue; returns the accepted-site mask.
+__device__ __forceinline__ unsigned delayed_chain(const WalkerDesc &w, Lds &L, const double *usb_g, const double *dsb_g, int cnt,
+                                  int S, ChainAcc &acc) {
+  const int lane = TID & 63, sp = lane >> 5, j = lane & 31;
+  lds_f64 *G = as_lds(L.dg) + sp * kDS * kDS;
+  const lds_f64 *usb = as_lds(usb_g);
+  const lds_f64 *dsb = as_lds(dsb_g) + sp * S;
+  const DelayedBufs B = dbufs(w, sp);
+  double *cacc = L.vec + sp * kDS;
+  int *accr = L.iscal + 64;
+  unsigned mask = 0;
+  int k = 0;
+  for (int r = 0; r < cnt; ++r) {
+    const double delta = dsb[r];
+    const double rsp = fma(delta, (double)G[r * kDS + r], 1.0);
+    const double ratio = halves_product(rsp);
+    // ratio and the uniform are identical in every lane: a scalar decision
+    if (__builtin_amdgcn_readfirstlane((int)(usb[r] < fabs(ratio)))) {
+      const double c = div_nr(delta, rsp);
+      if (j < cnt) {
+        const double grow = G[r * kDS + j], gcol = G[j * kDS + r];
+        B.rrec[k * kDS + j] = grow;
+        B.crec[k * kDS + j] = gcol;
+        if (j > r) {
+          const double cg = c * grow;
+          for (int i = r + 1; i < cnt; ++i) G[i * kDS + j] = fma(-cg, (double)G[i * kDS + r], (double)G[i * kDS + j]);
+        }
+      }
+      if (j == 0) cacc[k] = c;
+      if (lane == 0) accr[k] = r;
+      ++k;
+      mask |= 1u << r;
+      acc_ratio(acc, fabs(ratio));
+      wave_fence();
+    }
+  }
+  if (lane == 0) L.iscal[100] = k;
+  acc.nacc += k;
+  return mask;
+}
+
+// u~, w~ and the rank-k update of the inverse (all threads); ends with a
+// barrier.  The recursion coefficients c_t' G_t'[r_t', r_t] and
+// c_t' G_t'[r_t, r_t'] go to LDS (over the chunk matrix, no longer needed);
+// a thread carries one row of u~ (then c_t u~_t[a] goes to cu, the staging
+// half of the finished chunk) or one column b of w~ in registers, and the
+// thread of column b applies M[:, b] -= sum_t c_t u~_t w~_t[b].  KS >= k.
+template <int KS>
+__device__ __forceinline__ void delayed_epilogue(const WalkerDesc &w, Lds &L, double *cu, int cu_ld, int cu_sp) {
+  const int k = L.iscal[100];
+  if (k == 0) return;
+  const int *accr = L.iscal + 64;
+  double *CU = L.dg, *CW = L.dg + 2 * kDS * kDS;
+  for (int e = TID; e < 2 * k * k; e += kThreads) {
+    const int sp = e / (k * k), rem = e - sp * k * k, t2 = rem / k, t = rem - t2 * k;
+    const DelayedBufs B = dbufs(w, sp);
+    const double c2 = L.vec[sp * kDS + t2];
+    CU[sp * kDS * kDS + t2 * kDS + t] = c2 * B.rrec[t2 * kDS + accr[t]];
+    CW[sp * kDS * kDS + t2 * kDS + t] = c2 * B.crec[t2 * kDS + accr[t]];
+  }
+  SYNC();
+  const int m0 = w.ne[0], m1 = w.ne[1];
+  // rows of u~ (c_t u~_t[a] into cu[sp][t][a])
+  for (int f = TID; f < m0 + m1; f += kThreads) {
+    const int sp = f < m0 ? 0 : 1, a = f < m0 ? f : f - m0;
+    const DelayedBufs B = dbufs(w, sp);
+    const double *cf = CU + sp * kDS * kDS;
+    double v[KS];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      v[t] = 0.0;
+      if (t < k) {
+        double x = B.U[a * kDS + accr[t]];
+#pragma unroll
+        for (int t2 = 0; t2 < t; ++t2) x = fma(-cf[t2 * kDS + t], v[t2], x);
+        v[t] = x;
+        cu[(size_t)sp * cu_sp + t * cu_ld + a] = L.vec[sp * kDS + t] * x;
+      }
+    }
+  }
+  SYNC();
+  // columns of w~, then the update of column b of M
+  for (int f = TID; f < m0 + m1; f += kThreads) {
+    const int sp = f < m0 ? 0 : 1, b = f < m0 ? f : f - m0, m = sp ? m1 : m0;
+    const DelayedBufs B = dbufs(w, sp);
+    const double *cf = CW + sp * kDS * kDS;
+    double v[KS];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      v[t] = 0.0;
+      if (t < k) {
+        double x = B.W[accr[t] * w.mmax + b];
+#pragma unroll
+        for (int t2 = 0; t2 < t; ++t2) x = fma(-cf[t2 * kDS + t], v[t2], x);
+        v[t] = x;
+      }
+    }
+    double *M = sp ? L.Ms1 : L.Ms0;
+    const double *cus = cu + (size_t)sp * cu_sp;
+    // eight rows at a time: their loads of M are in flight together
+    int a = 0;
+    for (; a + 8 <= m; a += 8) {
+      double mv[8], s2[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        mv[q] = M[(size_t)(a + q) * m + b];
+        s2[q] = 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < KS; ++t)
+        if (t < k)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) s2[q] = fma(cus[t * cu_ld + a + q], v[t], s2[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) M[(size_t)(a + q) * m + b] = mv[q] - s2[q];
+    }
+    for (; a < m; ++a) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int t = 0; t < KS; ++t)
+        if (t < k) s2 = fma(cus[t * cu_ld + a], v[t], s2);
+      M[(size_t)a * m + b] -= s2;
+    }
+  }
+  SYNC();
+}
+
 // Stage chunk c (rows i0 .. i0+cnt-1) of slice l into buffer bufi: left rows
 // (Phi_L'^T = E_K^T Y_l, stored by the left-stack build), right rows when
 // streamed, fields and the flip uniforms.  Threads t0.. of the caller.
@@ -950,12 +1205,14 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
 template <int T, typename F>
 __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2],
                               bool resident, int mm, ChainAcc &acc) {
-  constexpr int TT = T > 0 ? T : 1;
+  constexpr bool kReg = T > 0 && T != kDelayed;   // register-tiled inverse
+  constexpr int TT = kReg ? T : 1;
   const int N = w.N, S = L.S;
   const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
   const int nch = (N + S - 1) / S;
   double M[2 * TT][TT];
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
+  static_assert(T == 0 || T == 1 || T == 2 || T == 4 || T == kDelayed, "chain shape");
   if constexpr (T == 0) {
     // column-major copies of the inverses for the chain (A, B are free here)
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -969,7 +1226,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
     }
     SYNC();
   }
-  if constexpr (T > 0) {
+  if constexpr (kReg) {
     if (TID < 64) {
       const int m = w.ne[sp];
       const double *Ms = sp ? L.Ms1 : L.Ms0;
@@ -985,7 +1242,45 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
   for (int l = l0; l <= l1; ++l) {
     if (l > l0)
       for (int s2 = 0; s2 < 2; ++s2) apply_diag(w, phi[s2], w.ne[s2], l, s2, false);
-    if (!(w.flags & 2)) {
+    if constexpr (T == kDelayed) {
+      if (!(w.flags & 2)) {
+        stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
+        SYNC();
+        for (int c = 0; c < nch; ++c) {
+          const int bufi = c & 1, i0 = c * S;
+          const int cnt = min(S, N - i0);
+          const double *xsb = L.xs + (size_t)bufi * 2 * S * mm;
+          auto prologue = [&](auto ks) {
+            constexpr int KS = decltype(ks)::value;
+            if (resident) {
+              const F *pr[2] = {phi[0] + (size_t)i0 * w.ne[0], phi[1] + (size_t)i0 * w.ne[1]};
+              const int lp[2] = {w.ne[0], w.ne[1]};
+              delayed_prologue<KS>(w, L, xsb, mm, pr, lp, cnt, S);
+            } else {
+              const double *pr[2] = {L.ps + (size_t)(bufi * 2) * S * mm, L.ps + (size_t)(bufi * 2 + 1) * S * mm};
+              const int lp[2] = {mm, mm};
+              delayed_prologue<KS>(w, L, xsb, mm, pr, lp, cnt, S);
+            }
+          };
+          if (S <= 8) prologue(std::integral_constant<int, 8>());
+          else prologue(std::integral_constant<int, 16>());
+          if (TID < 64) {
+            const unsigned mask = delayed_chain(w, L, L.us + bufi * S, L.dl + bufi * 2 * S, cnt, S, acc);
+            if (TID == 0) L.iscal[8 + bufi] = (int)mask;
+          } else {
+            if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+            if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+          }
+          SYNC();
+          // c u~ goes to this chunk's staging half, free once its rows are consumed
+          double *cu = L.xs + (size_t)bufi * 2 * S * mm;
+          if (S <= 8) delayed_epilogue<8>(w, L, cu, mm, S * mm);
+          else delayed_epilogue<16>(w, L, cu, mm, S * mm);
+        }
+        flush_chunk(w, L, l, (nch - 1) * S, (nch - 1) & 1, phi, resident, mm, 0, kThreads);
+        SYNC();
+      }
+    } else if (!(w.flags & 2)) {
       stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
       SYNC();
       for (int c = 0; c < nch; ++c) {
@@ -1022,7 +1317,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
     }
     for (int s2 = 0; s2 < 2; ++s2) apply_ek(w, L, phi[s2], w.ne[s2]);
   }
-  if constexpr (T > 0) {
+  if constexpr (kReg) {
     if (TID < 64) {
       const int m = w.ne[sp];
       double *Ms = sp ? L.Ms1 : L.Ms0;
@@ -1437,6 +1732,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
       case 1: forward_walker<1, F>(w, L, pl, want_aw); break;
       case 2: forward_walker<2, F>(w, L, pl, want_aw); break;
       case 4: forward_walker<4, F>(w, L, pl, want_aw); break;
+      case kDelayed: forward_walker<kDelayed, F>(w, L, pl, want_aw); break;
       default: forward_walker<0, F>(w, L, pl, want_aw); break;
     }
   }
@@ -2153,6 +2449,7 @@ hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int tile, int d
     case 1: return launch_forward_t<1>(d, n, p, do_measure, mixed, st);
     case 2: return launch_forward_t<2>(d, n, p, do_measure, mixed, st);
     case 4: return launch_forward_t<4>(d, n, p, do_measure, mixed, st);
+    case kDelayed: return launch_forward_t<kDelayed>(d, n, p, do_measure, mixed, st);
     case 0: return launch_forward_t<0>(d, n, p, do_measure, mixed, st);
     default: return launch_forward_t<-1>(d, n, p, do_measure, mixed, st);
   }
@@ -2171,21 +2468,21 @@ hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStre
 }
 hipError_t launch_green(const WalkerDesc *d, int mm, int b, int sp, double *G, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0});
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0, 0});
   lds_attr(k_green, by);
   hipLaunchKernelGGL(k_green, dim3(1), dim3(kThreads), by, st, d, mm, b, sp, G);
   return hipGetLastError();
 }
 hipError_t launch_flip_ratio(const WalkerDesc *d, int mm, int slice, int site, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0});
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0, 0});
   lds_attr(k_flip_ratio, by);
   hipLaunchKernelGGL(k_flip_ratio, dim3(1), dim3(kThreads), by, st, d, mm, slice, site);
   return hipGetLastError();
 }
 hipError_t launch_swap_ratio(const WalkerDesc *d, int mm, int sp, int k, int j, hipStream_t st) {
   mm = clamp_mm(mm);
-  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0});
+  const size_t by = lds_bytes(LdsPlan{mm, 0, 1, 0, 0, 0, mm > kLdsNe ? 1 : 0, 0});
   lds_attr(k_swap_ratio, by);
   hipLaunchKernelGGL(k_swap_ratio, dim3(1), dim3(kThreads), by, st, d, mm, sp, k, j);
   return hipGetLastError();

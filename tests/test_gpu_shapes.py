@@ -18,7 +18,7 @@ from paper_2601_08552_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-10
-TILES = (1, 2, 4, 0)
+TILES = (1, 2, 4, 0, 9)
 CHUNKS = (4, 8, 16, 32)
 
 
@@ -63,7 +63,7 @@ def _matches_oracle(g, o):
 
 
 def test_every_shape_follows_the_oracle(lq):
-    """All 16 (tile, chunk) shapes on one walker (Ne = 5 + 3, ragged last
+    """All 19 valid (tile, chunk) shapes on one walker (Ne = 5 + 3, ragged last
     chunk: N = 36) against the oracle's sweep."""
     lat, par = _case(5, 3)
     o = oracle.Walker(lat, par)
@@ -73,6 +73,12 @@ def test_every_shape_follows_the_oracle(lq):
         for c in CHUNKS:
             print(f"shape tile={t} chunk={c}", flush=True)
             g = lq.Walker(ctx, lat, par)
+            if t == 9 and c > 16:          # the delayed chain takes at most 16 sites per chunk
+                with pytest.raises(lq.LecqmcError) as e:
+                    g.set_shape(t, c)
+                assert e.value.code == lq.EINVAL
+                g.close()
+                continue
             g.set_shape(t, c)
             assert g.shape == (t, c)
             g.sweep(2, measure=True)
@@ -139,7 +145,7 @@ def test_autotune_keeps_the_chain(lq):
     for (tile, chunk, ms), w, (nu, nd, _) in zip(res, ws, specs):
         assert (tile, chunk) == w.shape
         assert tile in TILES and chunk in CHUNKS and ms > 0
-        assert tile == 0 or max(nu, nd) <= 8 * tile
+        assert tile in (0, 9) or max(nu, nd) <= 8 * tile
     for w, (st, tw, stats, meas) in zip(ws, before):
         for x, y in zip(w.state(), st):
             assert np.array_equal(np.asarray(x), np.asarray(y))
@@ -159,11 +165,11 @@ def test_autotune_keeps_the_chain(lq):
 
 
 def test_mixed_shape_batch_equals_alone(lq):
-    """Walkers with tiles 1, 2, 4 and 0 and different chunks in one batch
+    """Walkers with tiles 1, 2, 4, 0 and 9 (delayed) and different chunks in one batch
     (one launch that dispatches each walker's shape) against the same
     walkers swept alone."""
     specs = [(3, 2, 6, (1, 32)), (11, 7, 6, (2, 8)), (20, 18, 6, (4, 16)), (36, 4, 8, (0, 4)), (6, 6, 8, (4, 32)),
-             (13, 9, 6, (0, 8)), (27, 30, 6, (4, 8))]
+             (13, 9, 6, (0, 8)), (27, 30, 6, (4, 8)), (12, 5, 6, (9, 16)), (40, 33, 8, (9, 8))]
     ctx = lq.Context(0)
     alone, batch = [], []
     for (nu, nd, Ls, shp) in specs:
@@ -185,7 +191,8 @@ def test_mixed_shape_batch_equals_alone(lq):
     ctx.close()
 
 
-def test_large_ne_in_a_batch(lq):
+@pytest.mark.parametrize("big_shape", [(0, 4), (9, 16)])
+def test_large_ne_in_a_batch(lq, big_shape):
     """A walker with Ne > 64 (work matrices in device memory for the whole
     launch) batched with walkers that alone keep them in LDS: every walker
     matches itself swept alone, and the large one matches the oracle."""
@@ -197,6 +204,8 @@ def test_large_ne_in_a_batch(lq):
         cfg.append((lat, par))
         alone.append(lq.Walker(ctx, lat, par))
         batch.append(lq.Walker(ctx, lat, par))
+    for w in (alone[-1], batch[-1]):
+        w.set_shape(*big_shape)
     for a in alone:
         a.sweep(2, measure=True)
     lq.sweep_batch(batch, 2, measure=True)
