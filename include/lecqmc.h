@@ -94,11 +94,16 @@ typedef struct {
 } lecqmc_sweep_stats;
 
 /* Context: device ordinal, a borrowed hipStream_t (NULL = the library makes
- * its own), and the device-memory budget used for admission (0 = no limit). */
+ * its own, non-blocking, default priority), and the device-memory budget used
+ * for admission (0 = no limit).  Work of different contexts (streams) may
+ * overlap on the device. */
 int lecqmc_ctx_create(int device, void *hip_stream_or_null, size_t hbm_budget_bytes, lecqmc_ctx **out);
 /* Destroying a context that still owns walkers fails with LECQMC_ESTATE. */
 int lecqmc_ctx_destroy(lecqmc_ctx *ctx);
 int lecqmc_ctx_synchronize(lecqmc_ctx *ctx);
+/* Non-blocking: 1 when all work queued on the context's stream has finished,
+ * 0 while some is still running, a negative code on a device error. */
+int lecqmc_ctx_query(lecqmc_ctx *ctx);
 size_t lecqmc_ctx_bytes_in_use(const lecqmc_ctx *ctx);
 /* Per-phase device timing: when enabled, every sweep records HIP events on
  * the context's stream around its three launches (left stack, forward pass,

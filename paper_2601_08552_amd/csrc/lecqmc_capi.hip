@@ -38,6 +38,9 @@ struct lecqmc_ctx {
   size_t budget, used;
   WalkerDesc *d_batch;
   int batch_cap;
+  // earlier descriptor arrays, freed with the context: freeing device memory
+  // waits for the whole device, which would stall other contexts' work
+  std::vector<WalkerDesc *> old_batches;
   int live_walkers;
   bool timing;
   struct Rec { int phase; hipEvent_t a, b; };
@@ -52,6 +55,22 @@ static hipEvent_t take_event(lecqmc_ctx *c) {
   if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
   hipEvent_t e = nullptr;
   (void)hipEventCreate(&e);
+  return e;
+}
+
+// Host <-> device transfers and clears run on the context's own stream and
+// wait for that stream alone: work on the shared default stream can queue
+// behind other contexts' kernels (streams share the hardware queues).
+static hipError_t xfer(lecqmc_ctx *c, void *dst, const void *src, size_t n, hipMemcpyKind kind) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(dst, src, n, kind, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+static hipError_t zero(lecqmc_ctx *c, void *dst, size_t n) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(dst, 0, n, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return e;
 }
 
@@ -123,6 +142,7 @@ struct LaunchCfg {
   int slots;
   int mixed;      // FP32 storage in the sweep phases
   int tile;       // chain shape shared by all walkers, -1 if they differ
+  bool fits;      // the launch's fixed LDS part fits (always for one walker)
 };
 
 static LdsPlan plan_for(LdsPlan p, const std::vector<long> &needs, int bond_need, bool staged_if_streamed) {
@@ -172,12 +192,19 @@ static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
     if (w->h.tile == kDelayed) dgn = 4 * kDS * kDS;
   }
   if (!compact) bonds = 0;
-  const int gm = mm > kLdsNe ? 1 : 0;
+  // The fixed part of the plan takes each region's largest size over the
+  // walkers; when the Ne x Ne work matrices do not fit next to the rest, they
+  // move to the walkers' device memory (same arithmetic, other memory).
+  const LdsPlan worst{mm, 0, 1, 0, xs, smax, 0, dgn};
+  const int gm = (mm > kLdsNe || lds_bytes(worst) > kLdsLimit) ? 1 : 0;
   if (gm) slots = 1;   // one estimator workgroup per walker: the work matrices are one per walker
   const LdsPlan base{mm, 0, 0, 0, 0, 0, gm, 0}, fbase{mm, 0, 0, 0, xs, smax, gm, dgn};
+  LdsPlan fw = fbase;
+  fw.stage_ps = 1;
   return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(base, fock, bonds, false),
           base,                              plan_for(base, fresh, bonds, false), slots,
-          mixed,                             tile};
+          mixed,                             tile,
+          lds_bytes(fw) <= kLdsLimit};
 }
 
 // ---------------------------------------------------------------------------
@@ -331,7 +358,9 @@ extern "C" int lecqmc_ctx_create(int device, void *stream, size_t budget, lecqmc
     c->stream = (hipStream_t)stream;
     c->own_stream = false;
   } else {
-    hipError_t e = hipStreamCreate(&c->stream);
+    // non-blocking: the library's synchronous host copies (legacy default
+    // stream) then do not wait for kernels of other contexts' streams
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) { delete c; return fail(LECQMC_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
     c->own_stream = true;
   }
@@ -345,6 +374,7 @@ extern "C" int lecqmc_ctx_destroy(lecqmc_ctx *c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   if (c->d_batch) (void)hipFree(c->d_batch);
+  for (WalkerDesc *d : c->old_batches) (void)hipFree(d);
   for (auto &r : c->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -357,6 +387,18 @@ extern "C" int lecqmc_ctx_synchronize(lecqmc_ctx *c) {
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipStreamSynchronize(c->stream));
   return 0;
+}
+
+extern "C" int lecqmc_ctx_query(lecqmc_ctx *c) {
+  if (!c) return fail(LECQMC_EINVAL, "null context");
+  HIPCHK(hipSetDevice(c->device));
+  const hipError_t e = hipStreamQuery(c->stream);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();   // not an error: work is still in flight
+    return 0;
+  }
+  return fail(LECQMC_EDEVICE, "hipStreamQuery: %s", hipGetErrorString(e));
 }
 
 extern "C" size_t lecqmc_ctx_bytes_in_use(const lecqmc_ctx *c) { return c ? c->used : 0; }
@@ -389,7 +431,7 @@ extern "C" int lecqmc_ctx_phase_times(lecqmc_ctx *c, double ms[3], int64_t count
 // ---------------------------------------------------------------------------
 static int check_status(lecqmc_walker *w) {
   Scalars sc;
-  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   if (sc.status & 4) return fail(LECQMC_EUNSTABLE, "singular P^T B P or QR breakdown");
   return 0;
 }
@@ -549,9 +591,9 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   }
   auto cleanup = [&](int rc) { (void)hipFree(dmem); delete w; return rc; };
   auto up = [&](void *dst, const void *src, size_t n) -> hipError_t {
-    return n ? hipMemcpy(dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
+    return n ? xfer(ctx, dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
   };
-  hipError_t e = hipMemset(dmem, 0, p.total);
+  hipError_t e = zero(ctx, dmem, p.total);
   if (e == hipSuccess) e = up(col_start, hcol.data(), sizeof(int) * hcol.size());
   if (e == hipSuccess) e = up(bi, hbi.data(), sizeof(int) * hbi.size());
   if (e == hipSuccess) e = up(bj, hbj.data(), sizeof(int) * hbj.size());
@@ -632,13 +674,16 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
   }
   HIPCHK(hipSetDevice(c->device));
   if (c->batch_cap < n) {
+    const int cap = std::max(n, std::max(64, 2 * c->batch_cap));
+    WalkerDesc *nd = nullptr;
+    HIPCHK(hipMalloc(&nd, sizeof(WalkerDesc) * cap));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (c->d_batch) HIPCHK(hipFree(c->d_batch));
-    HIPCHK(hipMalloc(&c->d_batch, sizeof(WalkerDesc) * n));
-    c->batch_cap = n;
+    if (c->d_batch) c->old_batches.push_back(c->d_batch);
+    c->d_batch = nd;
+    c->batch_cap = cap;
   }
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
+  HIPCHK(xfer(c, c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
   struct Group {
     const WalkerDesc *d;
     int n;
@@ -647,6 +692,9 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
   std::vector<Group> groups;
   if (n64 > 0) groups.push_back({c->d_batch, n64, launch_cfg(order.data(), n64)});
   if (n > n64) groups.push_back({c->d_batch + n64, n - n64, launch_cfg(order.data() + n64, n - n64)});
+  for (const Group &g : groups)
+    if (!g.cf.fits) return fail(LECQMC_EINVAL, "the chain staging of these walkers does not fit one launch's LDS; "
+                                               "sweep them in separate batches or give them smaller chunks");
   auto each = [&](auto &&launch) {
     for (const Group &g : groups) {
       const hipError_t e = launch(g);
@@ -699,7 +747,7 @@ extern "C" int lecqmc_batch_create(lecqmc_walker *const *ws, int32_t n, lecqmc_b
   }
   WalkerDesc *d = nullptr;
   HIPCHK(hipMalloc(&d, sizeof(WalkerDesc) * n));
-  const hipError_t e = hipMemcpy(d, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice);
+  const hipError_t e = xfer(c, d, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d);
     return fail(LECQMC_EDEVICE, "upload: %s", hipGetErrorString(e));
@@ -712,6 +760,12 @@ extern "C" int lecqmc_batch_create(lecqmc_walker *const *ws, int32_t n, lecqmc_b
   b->n64 = n64;
   if (n64 > 0) b->cf64 = launch_cfg(order.data(), n64);
   if (n > n64) b->cfmx = launch_cfg(order.data() + n64, n - n64);
+  if ((n64 > 0 && !b->cf64.fits) || (n > n64 && !b->cfmx.fits)) {
+    (void)hipFree(d);
+    delete b;
+    return fail(LECQMC_EINVAL, "the chain staging of these walkers does not fit one launch's LDS; "
+                               "batch them separately or give them smaller chunks");
+  }
   for (lecqmc_walker *w : order) w->batches += 1;
   *out = b;
   return 0;
@@ -758,7 +812,7 @@ extern "C" int lecqmc_get_shape(const lecqmc_walker *w, int32_t *tile, int32_t *
 static int set_shape(lecqmc_walker *w, int tile, int chunk) {
   shape_apply(w->h, tile, chunk);
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemcpy(w->d_desc, &w->h, sizeof(WalkerDesc), hipMemcpyHostToDevice));
+  HIPCHK(xfer(w->ctx, w->d_desc, &w->h, sizeof(WalkerDesc), hipMemcpyHostToDevice));
   return 0;
 }
 
@@ -827,7 +881,7 @@ extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *til
     if (g.empty()) continue;
     hd.clear();
     for (auto *w : g) hd.push_back(w->h);
-    e = hipMemcpy(dd, hd.data(), sizeof(WalkerDesc) * hd.size(), hipMemcpyHostToDevice);
+    e = xfer(c, dd, hd.data(), sizeof(WalkerDesc) * hd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_left_stack(dd, (int)g.size(), launch_cfg(g.data(), (int)g.size()).left, pass, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
@@ -855,15 +909,14 @@ extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *til
           hd.push_back(w->h);
         }
         e = hipStreamSynchronize(st);
-        if (e == hipSuccess) e = hipMemcpy(dd, hd.data(), sizeof(WalkerDesc) * hd.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) {
-          const LaunchCfg cf = launch_cfg(g.data(), (int)g.size());
-          e = launch_forward(dd, (int)g.size(), cf.fwd, cf.tile, 0, pass, st);
-        }
+        if (e == hipSuccess) e = xfer(c, dd, hd.data(), sizeof(WalkerDesc) * hd.size(), hipMemcpyHostToDevice);
+        const LaunchCfg cf = launch_cfg(g.data(), (int)g.size());
+        if (!cf.fits) continue;   // this candidate cannot run these walkers in one launch
+        if (e == hipSuccess) e = launch_forward(dd, (int)g.size(), cf.fwd, cf.tile, 0, pass, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         for (size_t q = 0; q < g.size() && e == hipSuccess; ++q) {
           long long ticks = 0;
-          e = hipMemcpy(&ticks, &g[q]->h.sc->fwd_ticks, sizeof ticks, hipMemcpyDeviceToHost);
+          e = xfer(c, &ticks, &g[q]->h.sc->fwd_ticks, sizeof ticks, hipMemcpyDeviceToHost);
           const double ms = (double)ticks / (double)rate_khz;
           const int t = idx[q], cand = ti * 4 + ci;
           if (e == hipSuccess) {
@@ -907,7 +960,7 @@ extern "C" int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *s
   HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.fresh, 0, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
-  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   *log_abs_w = sc.fresh_logw;
   *sign = sc.fresh_sign;
   return (sc.status & 4) ? fail(LECQMC_EUNSTABLE, "singular P^T B P") : 0;
@@ -918,7 +971,7 @@ extern "C" int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
-  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   *log_abs_w = sc.logw + sc.fock_logw[0] + sc.fock_logw[1];
   *sign = sc.sign * sc.fock_sign[0] * sc.fock_sign[1];
   return 0;
@@ -930,7 +983,7 @@ extern "C" int lecqmc_measure(lecqmc_walker *w, double *out, int64_t n) {
   if (!w || !out || n < w->nobs) return fail(LECQMC_EINVAL, "output too small (%d needed)", w ? w->nobs : 0);
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemcpy(out, w->h.obs, sizeof(double) * w->nobs, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, out, w->h.obs, sizeof(double) * w->nobs, hipMemcpyDeviceToHost));
   return 0;
 }
 
@@ -938,7 +991,7 @@ extern "C" int lecqmc_reset_measure(lecqmc_walker *w) {
   if (!w) return fail(LECQMC_EINVAL, "null walker");
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemset(w->h.obs, 0, sizeof(double) * w->nobs));
+  HIPCHK(zero(w->ctx, w->h.obs, sizeof(double) * w->nobs));
   return 0;
 }
 
@@ -947,7 +1000,7 @@ extern "C" int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st) {
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
-  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   st->flip_attempts = sc.flip_att;
   st->flip_accepts = sc.flip_acc;
   st->swap_attempts = sc.swap_att[0] + sc.swap_att[1];
@@ -964,12 +1017,12 @@ extern "C" int lecqmc_get_state(lecqmc_walker *w, int8_t *fields, int32_t *occ_u
   if (!w) return fail(LECQMC_EINVAL, "null walker");
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  if (fields) HIPCHK(hipMemcpy(fields, w->h.s, (size_t)w->L * w->N, hipMemcpyDeviceToHost));
-  if (occ_up && w->ne[0]) HIPCHK(hipMemcpy(occ_up, w->h.occ[0], sizeof(int) * w->ne[0], hipMemcpyDeviceToHost));
-  if (occ_dn && w->ne[1]) HIPCHK(hipMemcpy(occ_dn, w->h.occ[1], sizeof(int) * w->ne[1], hipMemcpyDeviceToHost));
+  if (fields) HIPCHK(xfer(w->ctx, fields, w->h.s, (size_t)w->L * w->N, hipMemcpyDeviceToHost));
+  if (occ_up && w->ne[0]) HIPCHK(xfer(w->ctx, occ_up, w->h.occ[0], sizeof(int) * w->ne[0], hipMemcpyDeviceToHost));
+  if (occ_dn && w->ne[1]) HIPCHK(xfer(w->ctx, occ_dn, w->h.occ[1], sizeof(int) * w->ne[1], hipMemcpyDeviceToHost));
   if (sweep_counter) {
     Scalars sc;
-    HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+    HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
     *sweep_counter = sc.sweep;
   }
   return 0;
@@ -992,14 +1045,14 @@ extern "C" int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const in
   if (fields) {
     std::vector<int8_t> f((size_t)w->L * w->N);
     for (size_t t = 0; t < f.size(); ++t) f[t] = fields[t] > 0 ? 1 : -1;
-    HIPCHK(hipMemcpy(w->h.s, f.data(), f.size(), hipMemcpyHostToDevice));
+    HIPCHK(xfer(w->ctx, w->h.s, f.data(), f.size(), hipMemcpyHostToDevice));
   }
-  if (occ_up && w->ne[0]) HIPCHK(hipMemcpy(w->h.occ[0], occ_up, sizeof(int) * w->ne[0], hipMemcpyHostToDevice));
-  if (occ_dn && w->ne[1]) HIPCHK(hipMemcpy(w->h.occ[1], occ_dn, sizeof(int) * w->ne[1], hipMemcpyHostToDevice));
+  if (occ_up && w->ne[0]) HIPCHK(xfer(w->ctx, w->h.occ[0], occ_up, sizeof(int) * w->ne[0], hipMemcpyHostToDevice));
+  if (occ_dn && w->ne[1]) HIPCHK(xfer(w->ctx, w->h.occ[1], occ_dn, sizeof(int) * w->ne[1], hipMemcpyHostToDevice));
   Scalars sc;
-  HIPCHK(hipMemcpy(&sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
   sc.sweep = sweep_counter;
-  HIPCHK(hipMemcpy(w->h.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
+  HIPCHK(xfer(w->ctx, w->h.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
   const LaunchCfg cf = launch_cfg(&w, 1);
   HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.fresh, 1, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
@@ -1013,7 +1066,7 @@ extern "C" int lecqmc_green(lecqmc_walker *w, int32_t boundary, int32_t spin, do
   if (!w->d_green) HIPCHK(hipMalloc(&w->d_green, sizeof(double) * (size_t)w->N * w->N));
   HIPCHK(launch_green(w->d_desc, w->mmax, boundary, spin, w->d_green, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemcpy(G, w->d_green, sizeof(double) * (size_t)w->N * w->N, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, G, w->d_green, sizeof(double) * (size_t)w->N * w->N, hipMemcpyDeviceToHost));
   return check_status(w);
 }
 
@@ -1022,7 +1075,7 @@ extern "C" int lecqmc_flip_ratio(lecqmc_walker *w, int32_t slice, int32_t site, 
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(launch_flip_ratio(w->d_desc, w->mmax, slice, site, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemcpy(ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
   return check_status(w);
 }
 
@@ -1033,11 +1086,11 @@ extern "C" int lecqmc_swap_ratio(lecqmc_walker *w, int32_t spin, int32_t k, int3
   std::vector<int32_t> occ(ne);
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemcpy(occ.data(), w->h.occ[spin], sizeof(int) * ne, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, occ.data(), w->h.occ[spin], sizeof(int) * ne, hipMemcpyDeviceToHost));
   for (int a = 0; a < ne; ++a)
     if (occ[a] == j) return fail(LECQMC_EINVAL, "site %d is occupied", j);
   HIPCHK(launch_swap_ratio(w->d_desc, w->mmax, spin, k, j, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(hipMemcpy(ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(xfer(w->ctx, ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
   return check_status(w);
 }

@@ -14,6 +14,7 @@
 // QR update for particle removal / addition (SM Sec. I.A and I.B).
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lecqmc_internal.h"
@@ -2383,6 +2384,8 @@ static int clamp_mm(int mm) { return mm < 1 ? 1 : mm; }
 template <typename K>
 static void lds_attr(K kernel, size_t bytes) {
   if (bytes <= 65536) return;
+  static std::mutex mu;   // contexts may be driven from different host threads
+  std::lock_guard<std::mutex> guard(mu);
   static const void *keys[64];
   static size_t done[64];
   const void *k = (const void *)kernel;

@@ -32,7 +32,7 @@ EXPORTED = [
     "lecqmc_measure", "lecqmc_reset_measure", "lecqmc_get_stats", "lecqmc_get_state",
     "lecqmc_set_state", "lecqmc_green", "lecqmc_flip_ratio", "lecqmc_swap_ratio", "lecqmc_last_error",
     "lecqmc_batch_create", "lecqmc_batch_sweep", "lecqmc_batch_destroy",
-    "lecqmc_get_shape", "lecqmc_set_shape", "lecqmc_autotune",
+    "lecqmc_get_shape", "lecqmc_set_shape", "lecqmc_autotune", "lecqmc_ctx_query",
 ]
 
 
@@ -101,6 +101,7 @@ def load():
             "lecqmc_ctx_create": (C.c_int, [C.c_int, vp, C.c_size_t, C.POINTER(vp)]),
             "lecqmc_ctx_destroy": (C.c_int, [vp]),
             "lecqmc_ctx_synchronize": (C.c_int, [vp]),
+            "lecqmc_ctx_query": (C.c_int, [vp]),
             "lecqmc_ctx_bytes_in_use": (C.c_size_t, [vp]),
             "lecqmc_ctx_set_timing": (C.c_int, [vp, i32]),
             "lecqmc_ctx_phase_times": (C.c_int, [vp, vp, vp]),
@@ -184,6 +185,12 @@ class Context:
 
     def synchronize(self):
         _check(load().lecqmc_ctx_synchronize(self.h))
+
+    def query(self) -> bool:
+        """True when the context's stream has no work left (does not block)."""
+        rc = load().lecqmc_ctx_query(self.h)
+        _check(min(rc, 0))
+        return rc == 1
 
     def set_timing(self, enable=True):
         _check(load().lecqmc_ctx_set_timing(self.h, 1 if enable else 0))

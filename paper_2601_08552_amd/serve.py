@@ -68,6 +68,7 @@ class Server:
         self.step_ms: list = []
         self.updates = 0
         self.in_use = 0
+        self.on_finish = None           # optional callback(Result) when a request retires
 
     def submit(self, req: Request) -> None:
         self.pending.append(req)
@@ -94,6 +95,8 @@ class Server:
             if done >= req.sweeps:
                 self.results[req.rid] = Result(req.rid, w.measure(), w.stats(), w.tracked_weight(), w.state(),
                                                req.arrival, admitted, now)
+                if self.on_finish:
+                    self.on_finish(self.results[req.rid])
                 w.close()
                 self.in_use -= need
             else:
@@ -149,6 +152,167 @@ class Server:
         }
 
 
+# Forward-pass cost per site of one walker on MI355X (seconds), by Ne per
+# spin, from the chain-shape measurements; used only to route requests.
+_SITE_COST = ((8, 2.7e-7), (16, 5.0e-7), (32, 1.3e-6), (64, 1.2e-5), (128, 2.8e-5), (256, 1.0e-4))
+
+
+def sweep_cost(lattice, params) -> float:
+    """Rough seconds per sweep of one request: sites x slices x per-site cost."""
+    ne = max(params.n_up, params.n_dn, 1)
+    c = _SITE_COST[-1][1]
+    for n, v in _SITE_COST:
+        if ne <= n:
+            c = v
+            break
+    return lattice.n_sites * params.L_tau * c
+
+
+class LaneServer:
+    """Continuous batching over lanes.  Each lane is a context with its own
+    stream, its own resident batch and its own host thread; a request joins
+    the lane of its per-sweep cost (``edges`` in seconds), so a lane's
+    batched step is not held up by requests a thousand times larger, and the
+    lanes' kernels overlap on the device.  A lane thread admits its requests
+    first come, first served within the shared memory budget, sweeps its
+    batch once, waits for it on its own stream (the library call releases
+    the interpreter lock) and retires finished requests.  Walkers are freed
+    lazily, when a waiting request needs the memory: freeing device memory
+    can wait for the whole device."""
+
+    def __init__(self, ctxs, budget_bytes: int, max_active: int = 256, edges=(0.05, 0.5, 5.0)):
+        import threading
+        assert len(ctxs) == len(edges) + 1
+        self.edges = tuple(edges)
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.lanes = [dict(ctx=c, pending=deque(), active=[], graveyard=[], steps=[]) for c in ctxs]
+        self.lock = threading.Lock()
+        self.results: dict = {}
+        self.updates = 0
+        self.in_use = 0
+        self.n_active = 0
+        self.short = False              # a lane waits for memory: the others free their retired walkers
+        self.on_finish = None
+
+    def lane_of(self, req) -> int:
+        c = sweep_cost(req.lattice, req.params)
+        k = 0
+        while k < len(self.edges) and c >= self.edges[k]:
+            k += 1
+        return k
+
+    def _free(self, ln):
+        for w, need in ln["graveyard"]:
+            w.close()
+            with self.lock:
+                self.in_use -= need
+        ln["graveyard"] = []
+
+    def _admit(self, ln, now):
+        while ln["pending"] and ln["pending"][0].arrival <= now:
+            req = ln["pending"][0]
+            need = lecqmc.footprint_bytes(req.lattice, req.params)
+            if need == 0:
+                raise ValueError(f"request {req.rid}: invalid lattice or parameters")
+            if need > self.budget:
+                raise ValueError(f"request {req.rid}: footprint {need} exceeds the whole budget")
+            with self.lock:
+                ok = self.in_use + need <= self.budget and self.n_active < self.max_active
+                if ok:
+                    self.in_use += need
+                    self.n_active += 1
+                elif self.in_use + need > self.budget:
+                    self.short = True
+            if not ok:
+                if ln["graveyard"]:
+                    self._free(ln)
+                    continue
+                break
+            ln["pending"].popleft()
+            w = lecqmc.Walker(ln["ctx"], req.lattice, req.params)
+            ln["active"].append([req, w, 0, now, need])
+
+    def _retire(self, ln, now):
+        keep = []
+        for entry in ln["active"]:
+            req, w, done, admitted, need = entry
+            if done >= req.sweeps:
+                res = Result(req.rid, w.measure(), w.stats(), w.tracked_weight(), w.state(), req.arrival, admitted, now)
+                ln["graveyard"].append([w, need])
+                with self.lock:
+                    self.results[req.rid] = res
+                    self.n_active -= 1
+                if self.on_finish:
+                    self.on_finish(res)
+            else:
+                keep.append(entry)
+        ln["active"] = keep
+
+    def _lane(self, ln, clock, errors):
+        try:
+            while ln["pending"] or ln["active"]:
+                if self.short and ln["graveyard"]:
+                    self._free(ln)
+                    self.short = False
+                now = clock()
+                self._admit(ln, now)
+                if not ln["active"]:
+                    nxt = ln["pending"][0].arrival if ln["pending"] else now
+                    time.sleep(min(0.005, max(nxt - now, 2e-4)))
+                    continue
+                t0 = time.perf_counter()
+                lecqmc.sweep_batch([e[1] for e in ln["active"]], 1, measure=any(e[0].measure for e in ln["active"]))
+                ln["ctx"].synchronize()
+                ln["steps"].append((time.perf_counter() - t0) * 1e3)
+                n = 0
+                for e in ln["active"]:
+                    e[2] += 1
+                    n += e[0].lattice.n_sites * e[0].params.L_tau
+                with self.lock:
+                    self.updates += n
+                self._retire(ln, clock())
+        except BaseException as exc:    # reported by run() on the caller's thread
+            errors.append(exc)
+
+    def run(self, requests, clock=None) -> dict:
+        """Serve until every request has finished; ``clock`` gives seconds
+        since the start (wall clock by default)."""
+        import threading
+        lane_of = {}
+        for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
+            lane_of[r.rid] = self.lane_of(r)
+            self.lanes[lane_of[r.rid]]["pending"].append(r)
+        start = time.perf_counter()
+        clock = clock or (lambda: time.perf_counter() - start)
+        errors = []
+        threads = [threading.Thread(target=self._lane, args=(ln, clock, errors), daemon=True) for ln in self.lanes]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        for ln in self.lanes:
+            self._free(ln)
+        if errors:
+            raise errors[0]
+        wall = time.perf_counter() - start
+        lat = [r.latency for r in self.results.values()]
+        steps = [x for ln in self.lanes for x in ln["steps"]]
+        pct = lambda v: {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99))} if v else None
+        return {
+            "requests": len(self.results),
+            "wall_s": wall,
+            "updates_per_s": self.updates / wall if wall > 0 else 0.0,
+            "lanes": [{"requests": sum(1 for rid in self.results if lane_of[rid] == k), "steps": len(ln["steps"]),
+                       "step_ms": pct(ln["steps"]),
+                       "request_latency_s": pct([self.results[rid].latency for rid in self.results
+                                                 if lane_of[rid] == k])}
+                      for k, ln in enumerate(self.lanes)],
+            "step_ms": pct(steps),
+            "request_latency_s": pct(lat),
+        }
+
+
 def poisson_stream(n, rate, seed=0, lattices=(8, 12, 16, 24), ne_range=(2, 16), U_range=(2.0, 8.0),
                    beta_range=(2.0, 4.0), sweeps_range=(5, 20), dtau=0.05, n_stab=10):
     """A seeded stream of requests with exponential gaps (the serving
@@ -173,18 +337,38 @@ def poisson_stream(n, rate, seed=0, lattices=(8, 12, 16, 24), ne_range=(2, 16), 
 def main():
     import argparse
     import json
+    import sys
     ap = argparse.ArgumentParser(description="Serve a seeded Poisson stream of simulation requests.")
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--rate", type=float, default=50.0, help="arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--lattices", type=str, default="8,12,16,24", help="L of the L x L lattices, comma separated")
+    ap.add_argument("--ne", type=str, default="2,16", help="range of Ne per spin: lo,hi")
+    ap.add_argument("--beta", type=str, default="2,4", help="range of beta: lo,hi")
+    ap.add_argument("--sweeps", type=str, default="5,20", help="range of sweeps per request: lo,hi")
+    ap.add_argument("--lanes", type=int, default=4, help="cost lanes (1: one batch for all requests)")
     args = ap.parse_args()
-    ctx = lecqmc.Context(0)
-    srv = Server(ctx, int(args.budget_gb * 2**30))
-    rep = srv.run(poisson_stream(args.requests, args.rate, args.seed))
-    rep.update({"rate_per_s": args.rate, "budget_gb": args.budget_gb})
+    two = lambda t, f: tuple(f(x) for x in t.split(","))
+    reqs = poisson_stream(args.requests, args.rate, args.seed, lattices=two(args.lattices, int),
+                          ne_range=two(args.ne, int), beta_range=two(args.beta, float),
+                          sweeps_range=two(args.sweeps, int))
+    if args.lanes > 1:
+        edges = (0.05, 0.5, 5.0)[: args.lanes - 1] if args.lanes <= 4 else tuple(0.05 * 10 ** (k / 2) for k in range(args.lanes - 1))
+        ctxs = [lecqmc.Context(0) for _ in range(len(edges) + 1)]
+        srv = LaneServer(ctxs, int(args.budget_gb * 2**30), edges=edges)
+    else:
+        ctxs = [lecqmc.Context(0)]
+        srv = Server(ctxs[0], int(args.budget_gb * 2**30))
+    srv.on_finish = lambda r: print(f"[serve] request {r.rid} done: latency {r.latency:.2f} s", file=sys.stderr,
+                                    flush=True)
+    rep = srv.run(reqs)
+    rep.update({"rate_per_s": args.rate, "budget_gb": args.budget_gb, "lattices": args.lattices, "ne": args.ne,
+                "beta": args.beta, "sweeps": args.sweeps})
+    rep["server"] = f"{len(ctxs)} lane(s)"
     print(json.dumps(rep))
-    ctx.close()
+    for c in ctxs:
+        c.close()
 
 
 if __name__ == "__main__":

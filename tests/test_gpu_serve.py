@@ -48,3 +48,33 @@ def test_results_same_alone_and_in_the_mix(lq):
         w.close()
     assert srv.in_use == 0 and ctx.bytes_in_use() == 0
     ctx.close()
+
+
+def test_lanes_results_same_alone_and_in_the_mix(lq):
+    """Two cost lanes (two contexts, two streams) stepping independently:
+    every result still equals the request run alone."""
+    from paper_2601_08552_amd.serve import LaneServer, sweep_cost
+    reqs = _stream()
+    costs = sorted(sweep_cost(r.lattice, r.params) for r in reqs)
+    edge = costs[len(costs) // 2]
+    ctxs = [lq.Context(0), lq.Context(0)]
+    srv = LaneServer(ctxs, budget_bytes=1 << 34, edges=(edge,))
+    assert {srv.lane_of(r) for r in reqs} == {0, 1}
+    rep = srv.run(reqs)
+    assert rep["requests"] == len(reqs)
+    alone_ctx = lq.Context(0)
+    for r in reqs:
+        got = srv.results[r.rid]
+        w = lq.Walker(alone_ctx, r.lattice, r.params)
+        w.sweep(r.sweeps, measure=True)
+        for x, y in zip(got.state, w.state()):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), r.rid
+        lg, sg = got.tracked_weight
+        la, sa = w.tracked_weight()
+        assert sg == sa and abs(lg - la) <= 1e-10 * max(1.0, abs(la))
+        ma = w.measure()
+        assert np.max(np.abs(got.measure - ma)) <= 1e-9 * max(1.0, np.max(np.abs(ma)))
+        w.close()
+    assert srv.in_use == 0 and all(c.bytes_in_use() == 0 for c in ctxs)
+    for c in ctxs + [alone_ctx]:
+        c.close()

@@ -216,3 +216,26 @@ def test_large_ne_in_a_batch(lq, big_shape):
     o.sweep(2, measure=True)
     _matches_oracle(batch[-1], o)
     ctx.close()
+
+
+def test_batch_moves_matrices_out_of_lds(lq):
+    """Two walkers that each fit LDS alone but not together (Ne = 64 with the
+    inverse in memory, and Ne = 32 with a 32-site chunk): the launch moves its
+    Ne x Ne work matrices to device memory, and both walkers still match
+    themselves swept alone."""
+    specs = [((64, 40), 8, (0, 4)), ((32, 30), 8, (4, 32))]
+    ctx = lq.Context(0)
+    alone, batch = [], []
+    for (ne, Ls, shp) in specs:
+        lat, par = _case(ne[0], ne[1], Ls=Ls, beta=0.5, seed=70 + ne[0])
+        a, b = lq.Walker(ctx, lat, par), lq.Walker(ctx, lat, par)
+        a.set_shape(*shp)
+        b.set_shape(*shp)
+        alone.append(a)
+        batch.append(b)
+    for a in alone:
+        a.sweep(2, measure=True)
+    lq.sweep_batch(batch, 2, measure=True)
+    for a, b in zip(alone, batch):
+        assert _same(a, b)
+    ctx.close()

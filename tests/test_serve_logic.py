@@ -1,6 +1,8 @@
-"""Scheduling logic of the continuous-batching server on the CPU, with the
+"""Scheduling logic of the continuous-batching servers on the CPU, with the
 device library replaced by stand-ins (no GPU): admission order, the memory
 budget, slot limits, overlap of requests and retirement."""
+import time
+
 import numpy as np
 
 from paper_2601_08552_amd import serve
@@ -70,3 +72,78 @@ def test_admission_budget_slots_and_overlap(monkeypatch):
     # first come, first served
     adm = sorted(srv.results.values(), key=lambda x: x.rid)
     assert all(a.admitted <= b.admitted for a, b in zip(adm, adm[1:]))
+
+
+class _LaneCtx:
+    """A context whose step takes a set wall time (a stand-in for the GPU)."""
+
+    def __init__(self, step_s):
+        self.step_s = step_s
+        self.launches = 0
+
+    def synchronize(self):
+        time.sleep(self.step_s)
+
+
+class _LaneWalker(_Walker):
+    def __init__(self, ctx, lat, par):
+        super().__init__(ctx, lat, par)
+        self.ctx = ctx
+
+
+def _lane_sweep(ws, n, measure=False):
+    ctx = ws[0].ctx
+    assert all(w.ctx is ctx for w in ws)       # one lane per launch
+    ctx.launches += 1
+    for w in ws:
+        w.done += n
+
+
+def _lane_stream(seed, lattices, n):
+    return serve.poisson_stream(n, rate=2000.0, seed=seed, lattices=lattices, ne_range=(1, 4),
+                                beta_range=(0.5, 1.0), sweeps_range=(2, 5))
+
+
+def test_lanes_route_by_cost_and_step_independently(monkeypatch):
+    monkeypatch.setattr(serve.lecqmc, "Walker", _LaneWalker)
+    monkeypatch.setattr(serve.lecqmc, "sweep_batch", _lane_sweep)
+    monkeypatch.setattr(serve.lecqmc, "footprint_bytes", lambda lat, par: 1000 + lat.n_sites)
+    _Walker.live = 0
+    reqs = _lane_stream(9, (4, 6, 48), 16)
+    # two cost lanes: a step of the expensive lane lasts 0.2 s, of the cheap one 2 ms
+    ctxs = [_LaneCtx(0.002), _LaneCtx(0.2)]
+    srv = serve.LaneServer(ctxs, budget_bytes=10**9, edges=(1e-3,))
+    lanes = {r.rid: srv.lane_of(r) for r in reqs}
+    assert set(lanes.values()) == {0, 1}
+    rep = srv.run(reqs)
+    assert rep["requests"] == len(reqs) and _Walker.live == 0 and srv.in_use == 0
+    for r in reqs:
+        assert srv.results[r.rid].state[3] == r.sweeps
+        assert srv.results[r.rid].admitted >= r.arrival
+    # a cheap request never waited for a step of the expensive lane
+    for r in reqs:
+        if lanes[r.rid] == 0:
+            assert srv.results[r.rid].latency < 0.2, (r.rid, srv.results[r.rid].latency)
+    assert rep["lanes"][0]["requests"] + rep["lanes"][1]["requests"] == len(reqs)
+
+
+def test_lanes_keep_the_budget(monkeypatch):
+    monkeypatch.setattr(serve.lecqmc, "Walker", _LaneWalker)
+    monkeypatch.setattr(serve.lecqmc, "sweep_batch", _lane_sweep)
+    monkeypatch.setattr(serve.lecqmc, "footprint_bytes", lambda lat, par: 1000 + lat.n_sites)
+    _Walker.live = 0
+    reqs = _lane_stream(4, (4, 6, 40), 12)
+    budget = 3 * 2600
+    srv = serve.LaneServer([_LaneCtx(0.001), _LaneCtx(0.004)], budget_bytes=budget, edges=(1e-3,))
+    peak = {"mem": 0}
+    admit = srv._admit
+
+    def watched(ln, now):
+        admit(ln, now)
+        with srv.lock:
+            peak["mem"] = max(peak["mem"], srv.in_use)
+
+    srv._admit = watched
+    rep = srv.run(reqs)
+    assert rep["requests"] == len(reqs) and _Walker.live == 0
+    assert 0 < peak["mem"] <= budget
