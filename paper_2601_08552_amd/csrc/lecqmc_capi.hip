@@ -121,9 +121,10 @@ static bool shape_valid(int mmax, int tile, int chunk) {
   if (tile > 0 && tile != kDelayed && mmax > 8 * tile) return false;
   if (!(chunk == 4 || chunk == 8 || chunk == 16 || chunk == 32)) return false;
   if (tile == kDelayed && chunk > 16) return false;   // the delayed chain's registers hold 16 sites
-  // both staging buffers (streamed walker) must fit next to the fixed layout
-  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, mmax > kLdsNe ? 1 : 0,
-                  tile == kDelayed ? 4 * kDS * kDS : 0};
+  // both staging buffers (streamed walker) must fit next to the fixed layout,
+  // with the Ne x Ne work matrices moved to device memory if need be (the
+  // launch planner does that when they do not fit)
+  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, 1, tile == kDelayed ? 4 * kDS * kDS : 0};
   return lds_bytes(p) <= kLdsLimit;
 }
 static void shape_apply(WalkerDesc &h, int tile, int chunk) {
@@ -195,10 +196,19 @@ static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
   // The fixed part of the plan takes each region's largest size over the
   // walkers; when the Ne x Ne work matrices do not fit next to the rest, they
   // move to the walkers' device memory (same arithmetic, other memory).
-  const LdsPlan worst{mm, 0, 1, 0, xs, smax, 0, dgn};
-  const int gm = (mm > kLdsNe || lds_bytes(worst) > kLdsLimit) ? 1 : 0;
-  if (gm) slots = 1;   // one estimator workgroup per walker: the work matrices are one per walker
-  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm, 0}, fbase{mm, 0, 0, 0, xs, smax, gm, dgn};
+  // Placement of the Ne x Ne work matrices per launch kind: the first of all
+  // four in LDS, the two inverses in LDS, none -- the forward pass also
+  // holds the chain staging, the other phases do not
+  auto place = [&](LdsPlan worst) {
+    worst.gm = 0;
+    if (mm <= kLdsNe && lds_bytes(worst) <= kLdsLimit) return 0;
+    worst.gm = 2;
+    return lds_bytes(worst) <= kLdsLimit ? 2 : 1;
+  };
+  const int gmf = place(LdsPlan{mm, 0, 1, 0, xs, smax, 0, dgn});
+  const int gm = place(LdsPlan{mm, 0, 0, 0, 0, 0, 0, 0});
+  if (gm) slots = 1;   // one estimator workgroup per walker: its work matrices are one per walker
+  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm, 0}, fbase{mm, 0, 0, 0, xs, smax, gmf, dgn};
   LdsPlan fw = fbase;
   fw.stage_ps = 1;
   return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(base, fock, bonds, false),

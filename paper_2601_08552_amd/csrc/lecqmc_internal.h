@@ -92,8 +92,8 @@ struct WalkerDesc {
   Scalars *sc;
 };
 
-// LDS plan of one launch: the largest Ne (mm; above kLdsNe the Ne x Ne work
-// matrices move to device memory, gm = 1), the room for resident Slater
+// LDS plan of one launch: the largest Ne (mm; the Ne x Ne work matrices move
+// to device memory in part or whole when they do not fit, gm), the room for resident Slater
 // blocks (phi_elems doubles; a walker whose blocks fit keeps them there, the
 // others stream them), right-row staging buffers (forward pass with a
 // streamed walker), the compact bond tables (bond_words, 0 = read from device
@@ -102,7 +102,8 @@ struct WalkerDesc {
 // forward pass).
 struct LdsPlan {
   int mm, phi_elems, stage_ps, bond_words, xs_elems, smax;
-  int gm;   // 1: the Ne x Ne work matrices live in each walker's bigm, not in LDS
+  int gm;   // Ne x Ne work matrices: 0 all four in LDS, 2 the inverses in LDS and the scratch
+            // pair in each walker's bigm, 1 all four in bigm
   int dgn;  // LDS doubles for the delayed chain's chunk and coefficient matrices (4 kDS^2, or 0)
 };
 // LDS doubles that a walker's resident blocks of `entries` elements need

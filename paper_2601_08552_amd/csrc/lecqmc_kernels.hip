@@ -80,7 +80,8 @@ struct Lds {
 __host__ __device__ inline int vec_len(int mm) { return mm > 64 ? mm : 64; }
 __host__ __device__ inline size_t lds_doubles_fixed(const LdsPlan &p) {
   const size_t mm = p.mm < 1 ? 1 : p.mm, S = p.smax > 0 ? p.smax : 0, vs = vec_len((int)mm);
-  return 256 + 64 + (p.gm ? 0 : 4 * mm * mm) + 8 * vs + 4 * vs + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S +
+  const size_t mats = p.gm == 1 ? 0 : (p.gm == 2 ? 2 : 4) * mm * mm;
+  return 256 + 64 + mats + 8 * vs + 4 * vs + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S +
          4 * S + (2 * S + 7) / 8 + (size_t)p.dgn;
 }
 
@@ -99,11 +100,12 @@ __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   const int vs = vec_len(mm);
   L.red = p; p += 256;
   L.scal = p; p += 64;
-  if (pl.gm) {
-    L.Ms0 = L.Ms1 = L.A = L.B = nullptr;   // bound per walker by bind_mats
-  } else {
+  L.Ms0 = L.Ms1 = L.A = L.B = nullptr;   // those not in LDS are bound per walker by bind_mats
+  if (pl.gm != 1) {
     L.Ms0 = p; p += mm * mm;
     L.Ms1 = p; p += mm * mm;
+  }
+  if (pl.gm == 0) {
     L.A = p; p += mm * mm;
     L.B = p; p += mm * mm;
   }
@@ -124,15 +126,18 @@ __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   L.cs = nullptr;
   return L;
 }
-// Ne x Ne work matrices in device memory (plans with gm = 1): slot 0 for
-// kernels with one workgroup per walker, the spin for those with one per
-// (walker, spin).  The matrices are addressed with the walker's own Ne.
+// Ne x Ne work matrices in device memory (plans with gm = 1: all four; gm =
+// 2: the scratch pair A, B): slot 0 for kernels with one workgroup per
+// walker, the spin for those with one per (walker, spin).  The matrices are
+// addressed with the walker's own Ne.
 __device__ __forceinline__ void bind_mats(Lds &L, const WalkerDesc &w, const LdsPlan &pl, int slot) {
-  if (!pl.gm) return;
+  if (pl.gm == 0) return;
   const size_t q = (size_t)w.mmax * w.mmax;
   double *base = w.bigm + (size_t)slot * 4 * q;
-  L.Ms0 = base;
-  L.Ms1 = base + q;
+  if (pl.gm == 1) {
+    L.Ms0 = base;
+    L.Ms1 = base + q;
+  }
   L.A = base + 2 * q;
   L.B = base + 3 * q;
 }
