@@ -1,12 +1,15 @@
 """Continuous-batching service over the C ABI.
 
 Independent simulation requests (lattice, particle numbers, U, beta, sweep
-count, seed) arrive over time.  The server keeps every admitted request as a
-walker resident in device memory and advances all of them together, one
-batched sweep per step.  A request is admitted as soon as it has arrived,
-a slot is free and its device footprint (``lecqmc_footprint_bytes``) fits the
-remaining budget.  Requests that arrive while others run therefore join the
-next step, and retired walkers release their memory and slot at once.
+count, seed) arrive over time.  A server keeps every admitted request as a
+walker resident in device memory and advances the resident walkers in
+batched sweeps.  A request is admitted as soon as it has arrived, a slot is
+free and its device footprint (``lecqmc_footprint_bytes``) fits the
+remaining budget, so requests that arrive while others run join the next
+step.  ``Server`` runs one batch (one sweep of every resident walker per
+step; retired walkers release their memory at once).  ``LaneServer`` runs
+one batch per cost lane, each on its own context, stream and host thread,
+so that small requests are not held up by steps of much larger ones.
 
 Every walker's Markov chain depends only on its own seed, so a request's
 result is the same whether it runs alone or in a mix: the integer state
