@@ -111,3 +111,19 @@ def test_graph_capture_replays_match_eager(lq):
     ba.close()
     bb.close()
     ctx.close()
+
+
+def test_context_query(lq):
+    """lecqmc_ctx_query does not block: it reports work in flight on the
+    context's stream, and the empty stream once synchronised."""
+    ctx = lq.Context(0)
+    lat = W.square_lattice(16)
+    par = W.Params(U=4.0, beta=4.0, dtau=0.05, n_stab=10, n_up=6, n_dn=6, seed=5)
+    w = lq.Walker(ctx, lat, par)
+    assert ctx.query()
+    w.sweep(3)
+    busy = ctx.query()            # usually False: three sweeps take milliseconds
+    ctx.synchronize()
+    assert ctx.query()
+    assert busy in (True, False)
+    ctx.close()
