@@ -92,20 +92,24 @@ size_t lds_bytes(const LdsPlan &p) {
 
 extern __shared__ double lds_raw[];
 
+// LEAN: the plan is known to keep all four work matrices in LDS and to have
+// no delayed-chain area (launches of register-tiled walkers), which keeps
+// fewer values live in the kernels that use it.
+template <bool LEAN = false>
 __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   const int mm = pl.mm < 1 ? 1 : pl.mm;
   const int S = pl.smax > 0 ? pl.smax : 0;
   Lds L;
   double *p = lds_raw;
-  const int vs = vec_len(mm);
+  const int vs = LEAN ? 64 : vec_len(mm);
   L.red = p; p += 256;
   L.scal = p; p += 64;
   L.Ms0 = L.Ms1 = L.A = L.B = nullptr;   // those not in LDS are bound per walker by bind_mats
-  if (pl.gm != 1) {
+  if (LEAN || pl.gm != 1) {
     L.Ms0 = p; p += mm * mm;
     L.Ms1 = p; p += mm * mm;
   }
-  if (pl.gm == 0) {
+  if (LEAN || pl.gm == 0) {
     L.A = p; p += mm * mm;
     L.B = p; p += mm * mm;
   }
@@ -117,7 +121,12 @@ __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   L.us = p; p += 2 * S;
   L.dl = p; p += 4 * S;
   L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
-  L.dg = pl.dgn > 0 ? p : nullptr; p += pl.dgn;
+  if (LEAN) {
+    L.dg = nullptr;
+  } else {
+    L.dg = pl.dgn > 0 ? p : nullptr;
+    p += pl.dgn;
+  }
   L.phi = pl.phi_elems > 0 ? p : nullptr; p += pl.phi_elems;
   L.bonds = pl.bond_words > 0 ? p : nullptr; p += (pl.bond_words + 1) / 2;
   L.iscal = reinterpret_cast<int *>(p);
@@ -1603,11 +1612,13 @@ __global__ void __launch_bounds__(kThreads) k_fresh_weight(const WalkerDesc *__r
 // LS[n] = P.  Y stays in LDS when it fits.
 // F: storage of the propagated block and of the stored left states (FP64, or
 // FP32 for mixed-precision walkers); the QR and the stack LS stay FP64.
-template <typename F>
+// LEAN: the plan keeps the work matrices in LDS (Ne <= 64) -- the layout of
+// the common case, with fewer values live.
+template <typename F, bool LEAN>
 __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
-  Lds L = carve(pl);
-  bind_mats(L, w, pl, blockIdx.x & 1);
+  Lds L = carve<LEAN>(pl);
+  if constexpr (!LEAN) bind_mats(L, w, pl, blockIdx.x & 1);
   load_bonds(w, L, pl.bond_words);
   const int N = w.N;
   {
@@ -1640,7 +1651,8 @@ __global__ void __launch_bounds__(kThreads) k_left_stack(const WalkerDesc *__res
 template <int TSEL, typename F>
 __device__ __forceinline__ void forward_walker(const WalkerDesc &w, Lds &L, const LdsPlan &pl, int want_aw) {
   const int N = w.N, n = w.nblk;
-  const int xld = w.xld;
+  // staged-row stride: 8T for a register tile (a compile-time constant)
+  const int xld = (TSEL == 1 || TSEL == 2 || TSEL == 4) ? 8 * TSEL : w.xld;
   const bool resident =
       L.phi != nullptr && phi_doubles((long)N * (w.ne[0] + w.ne[1]), (int)sizeof(F)) <= (long)pl.phi_elems;
   const uint32_t sweep = (uint32_t)(w.sc->sweep + 1);
@@ -1727,8 +1739,9 @@ template <int TSEL, typename F>
 __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restrict__ descs, LdsPlan pl, int want_aw) {
   const WalkerDesc &w = descs[blockIdx.x];
   const long long t0 = wall_clock64();
-  Lds L = carve(pl);
-  bind_mats(L, w, pl, 0);
+  constexpr bool kLean = TSEL == 1 || TSEL == 2 || TSEL == 4;
+  Lds L = carve<kLean>(pl);
+  if constexpr (!kLean) bind_mats(L, w, pl, 0);
   L.S = w.chunk;
   load_bonds(w, L, pl.bond_words);
   if constexpr (TSEL >= 0) {
@@ -2249,12 +2262,13 @@ __device__ int nth_empty(const WalkerDesc &w, int sp, int nth, Lds &L) {
 
 // One workgroup per (walker, spin): the two species have separate stacks,
 // inverses and occupations, so their swap sequences are independent.
-template <typename F>
+// LEAN as for k_left_stack.
+template <typename F, bool LEAN>
 __global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *__restrict__ descs, LdsPlan pl) {
   const WalkerDesc &w = descs[blockIdx.x >> 1];
   const int sp = blockIdx.x & 1;
-  Lds L = carve(pl);
-  bind_mats(L, w, pl, sp);
+  Lds L = carve<LEAN>(pl);
+  if constexpr (!LEAN) bind_mats(L, w, pl, sp);
   load_bonds(w, L, pl.bond_words);
   // column storage: LDS when the plan holds N entries of F, else device memory
   F *fw = (L.phi && (size_t)pl.phi_elems * sizeof(double) >= (size_t)w.N * sizeof(F))
@@ -2417,15 +2431,24 @@ hipError_t launch_fresh_weight(const WalkerDesc *d, int n, LdsPlan p, int set_tr
   hipLaunchKernelGGL(k_fresh_weight, dim3(n), dim3(kThreads), b, st, d, p, set_tracked);
   return hipGetLastError();
 }
+// the lean kernels of the per-spin phases: every work matrix in LDS, no
+// delayed-chain area, vectors of 64
+static bool lean_plan(const LdsPlan &p) { return p.gm == 0 && p.dgn == 0 && p.mm <= 64; }
+template <typename F, bool LEAN>
+static void launch_left_t(const WalkerDesc *d, int n, const LdsPlan &p, size_t b, hipStream_t st) {
+  lds_attr(k_left_stack<F, LEAN>, b);
+  hipLaunchKernelGGL((k_left_stack<F, LEAN>), dim3(2 * n), dim3(kThreads), b, st, d, p);
+}
 hipError_t launch_left_stack(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStream_t st) {
   p = clamp_plan(p);
   const size_t b = lds_bytes(p);
+  const bool lean = lean_plan(p);
   if (mixed) {
-    lds_attr(k_left_stack<float>, b);
-    hipLaunchKernelGGL(k_left_stack<float>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+    if (lean) launch_left_t<float, true>(d, n, p, b, st);
+    else launch_left_t<float, false>(d, n, p, b, st);
   } else {
-    lds_attr(k_left_stack<double>, b);
-    hipLaunchKernelGGL(k_left_stack<double>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+    if (lean) launch_left_t<double, true>(d, n, p, b, st);
+    else launch_left_t<double, false>(d, n, p, b, st);
   }
   return hipGetLastError();
 }
@@ -2453,6 +2476,9 @@ static hipError_t launch_forward_t(const WalkerDesc *d, int n, LdsPlan p, int wa
 }
 hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int tile, int do_measure, int mixed, hipStream_t st) {
   p = clamp_plan(p);
+  // the register-tile kernels assume the lean layout (all work matrices in
+  // LDS, no delayed-chain area, vectors of 64)
+  if ((tile == 1 || tile == 2 || tile == 4) && !lean_plan(p)) tile = -1;
   switch (tile) {
     case 1: return launch_forward_t<1>(d, n, p, do_measure, mixed, st);
     case 2: return launch_forward_t<2>(d, n, p, do_measure, mixed, st);
@@ -2462,15 +2488,21 @@ hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int tile, int d
     default: return launch_forward_t<-1>(d, n, p, do_measure, mixed, st);
   }
 }
+template <typename F, bool LEAN>
+static void launch_fock_t(const WalkerDesc *d, int n, const LdsPlan &p, size_t b, hipStream_t st) {
+  lds_attr(k_fock<F, LEAN>, b);
+  hipLaunchKernelGGL((k_fock<F, LEAN>), dim3(2 * n), dim3(kThreads), b, st, d, p);
+}
 hipError_t launch_fock(const WalkerDesc *d, int n, LdsPlan p, int mixed, hipStream_t st) {
   p = clamp_plan(p);
   const size_t b = lds_bytes(p);
+  const bool lean = lean_plan(p);
   if (mixed) {
-    lds_attr(k_fock<float>, b);
-    hipLaunchKernelGGL(k_fock<float>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+    if (lean) launch_fock_t<float, true>(d, n, p, b, st);
+    else launch_fock_t<float, false>(d, n, p, b, st);
   } else {
-    lds_attr(k_fock<double>, b);
-    hipLaunchKernelGGL(k_fock<double>, dim3(2 * n), dim3(kThreads), b, st, d, p);
+    if (lean) launch_fock_t<double, true>(d, n, p, b, st);
+    else launch_fock_t<double, false>(d, n, p, b, st);
   }
   return hipGetLastError();
 }
