@@ -1,0 +1,71 @@
+"""The small plain configuration on the GPU: 4x4 periodic Hubbard, t = 1,
+2 up + 2 down, beta = 4, dtau = 0.1 (40 slices), a QR every 10 slices, 200
+sweeps after a warm-up.  At U = 4 the whole run must be the oracle's run
+(identical Markov chain, weights within 1e-10, estimators within 1e-9).  At
+U = 0 the binned estimators must agree with the canonical free-fermion
+values within 4 sigma (jackknife): the kinetic energy per site is twice the
+one-spin 2-particle value from exact diagonalisation, and the double
+occupancy is 1/64 (uniform density 2/16 per spin on the torus).
+"""
+import numpy as np
+import pytest
+
+import exact
+import oracle
+from paper_2601_08552_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lq():
+    from paper_2601_08552_amd import lecqmc
+    lecqmc.load()
+    return lecqmc
+
+
+def test_small_config_200_sweeps_follow_the_oracle(lq):
+    lat, par = W.config_small(U=4.0, seed=1)
+    ctx = lq.Context(0)
+    g = lq.Walker(ctx, lat, par)
+    o = oracle.Walker(lat, par)
+    for w in (g, o):
+        w.sweep(20)
+        w.reset_measure()
+        w.sweep(200, measure=True)
+    fg, ug, dg, sg = g.state()
+    fo, uo, do, so = o.state()
+    assert sg == so == 220
+    assert np.array_equal(fg, fo) and np.array_equal(ug, uo) and np.array_equal(dg, do)
+    lg, sgg = g.tracked_weight()
+    lo, soo = o.tracked_weight()
+    assert sgg == soo and abs(lg - lo) <= 1e-10 * max(1.0, abs(lo))
+    stg, sto = g.stats(), o.stats()
+    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts"):
+        assert stg[k] == sto[k], k
+    mg, mo = g.measure(), o.measure()
+    assert mg[1] == mo[1] == 200 * 3          # three interior boundaries per sweep
+    assert np.max(np.abs(mg - mo)) < 1e-9 * max(1.0, np.max(np.abs(mo)))
+    ctx.close()
+
+
+def test_small_config_free_fermions_against_closed_form(lq):
+    lat, par = W.config_small(U=0.0, seed=4)
+    ctx = lq.Context(0)
+    g = lq.Walker(ctx, lat, par)
+    g.sweep(20)
+    g.reset_measure()
+    bins = []
+    for _ in range(20):
+        g.sweep(10, measure=True)
+        bins.append(g.measure())
+        g.reset_measure()
+    bins = np.array(bins)
+    one_spin = exact.SectorED(lat, W.Params(U=0.0, beta=par.beta, dtau=par.dtau, n_stab=par.n_stab,
+                                             n_up=2, n_dn=0))
+    ekin_ref = 2.0 * one_spin.ekin_per_site()
+    for idx, ref in ((3, ekin_ref), (2, 1.0 / 64.0)):
+        est, err = exact.jackknife_ratio(bins[:, idx], bins[:, 0])
+        assert abs(est - ref) <= 4.0 * err + 1e-12, (idx, est, err, ref)
+    assert g.stats()["swap_accepts"] > 0
+    ctx.close()
