@@ -363,9 +363,24 @@ __device__ void fill_P(const WalkerDesc &w, int sp, F *X) {
   SYNC();
 }
 
+// dst[0..n) = src[0..n); eight loads are issued before their stores, since
+// the compiler cannot tell that dst and src do not overlap
 template <typename D, typename S>
 __device__ void copy_global(D *dst, const S *src, size_t n) {
-  for (size_t t = TID; t < n; t += kThreads) dst[t] = (D)src[t];
+  constexpr int U = 8;
+  for (size_t t0 = TID; t0 < n; t0 += (size_t)U * kThreads) {
+    D v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t t = t0 + (size_t)u * kThreads;
+      v[u] = t < n ? (D)src[t] : (D)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t t = t0 + (size_t)u * kThreads;
+      if (t < n) dst[t] = v[u];
+    }
+  }
   SYNC();
 }
 
@@ -487,6 +502,88 @@ __device__ void right_tri_mul(const TI *in, double *out, double *out2, int N, in
   SYNC();
 }
 
+// X <- X * Ri in place (Ri upper triangular), one thread per row: row i of
+// the product needs only row i of X.  A row of at most MR entries is held in
+// registers; a longer one is rewritten from its last column to its first, so
+// that column c still reads the unmodified entries 0..c.  Each entry is
+// summed in the order right_tri_mul uses.  The result also goes to out2 (if
+// set).
+template <int MR, typename P>
+__device__ __forceinline__ void tri_mul_rows_t(P X, double *out2, int N, int m, const double *Ri) {
+  for (int i = TID; i < N; i += kThreads) {
+    P row = X + (size_t)i * m;
+    double *o2 = out2 ? out2 + (size_t)i * m : nullptr;
+    if (m <= MR) {
+      double r[MR];
+#pragma unroll
+      for (int a = 0; a < MR; ++a) r[a] = a < m ? (double)row[a] : 0.0;
+#pragma unroll
+      for (int c = 0; c < MR; ++c) {
+        if (c < m) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a <= c; ++a) s += r[a] * Ri[a * m + c];
+          row[c] = s;
+          if (o2) o2[c] = s;
+        }
+      }
+    } else {
+      for (int c = m - 1; c >= 0; --c) {
+        double s = 0.0;
+        for (int a = 0; a <= c; ++a) s += (double)row[a] * Ri[a * m + c];
+        row[c] = s;
+        if (o2) o2[c] = s;
+      }
+    }
+  }
+  SYNC();
+}
+template <int MR>
+__device__ __forceinline__ void tri_mul_rows(double *X, double *out2, int N, int m, const double *Ri) {
+  if (in_lds(X)) tri_mul_rows_t<MR>(as_lds(X), out2, N, m, Ri);
+  else tri_mul_rows_t<MR>(X, out2, N, m, Ri);
+}
+
+// CholeskyQR2 of an FP64 block in its own storage: X (N x m) -> Q, also
+// stored to out2 (if set).  Returns false, with X untouched, when the first
+// Gram matrix is not numerically positive definite.  Same arithmetic as the
+// general path below, without its device-memory intermediates.
+template <int MR>
+__device__ bool cholqr_inplace(double *X, double *out2, double *Vout, double *Vacc, int N, int m, Lds &L,
+                               Scalars *sc, double *ld) {
+  gram(X, m, X, m, N, L.A, L.red);
+  if (!cholesky(L.A, m, L.scal)) return false;
+  for (int t = TID; t < m * m; t += kThreads) {
+    const int a = t / m, c = t % m;
+    Vacc[t] = c >= a ? L.A[t] : 0.0;
+  }
+  tri_inverse(L.A, m, L.B);
+  tri_mul_rows<MR>(X, nullptr, N, m, L.B);
+  gram(X, m, X, m, N, L.A, L.red);
+  if (!cholesky(L.A, m, L.scal)) {
+    if (TID == 0) sc->status |= 4;
+  }
+  tri_inverse(L.A, m, L.B);
+  tri_mul_rows<MR>(X, out2, N, m, L.B);
+  for (int t = TID; t < m * m; t += kThreads) {
+    const int a = t / m, c = t % m;
+    double s = 0.0;
+    for (int b = a; b <= c; ++b) s += L.A[a * m + b] * Vacc[b * m + c];
+    L.B[t] = c >= a ? s : 0.0;
+  }
+  SYNC();
+  for (int t = TID; t < m * m; t += kThreads) {
+    Vacc[t] = L.B[t];
+    if (Vout) Vout[t] = L.B[t];
+  }
+  SYNC();
+  double s = 0.0;
+  for (int a = 0; a < m; ++a) s += log(Vacc[a * m + a]);
+  SYNC();
+  *ld = s;
+  return true;
+}
+
 // Thin QR with positive diagonal by Cholesky QR, repeated (CholeskyQR2;
 // a shifted first pass and a third pass when the Gram matrix is not
 // numerically positive definite).  Phi (N x m) -> Q in q1 (and q2); the
@@ -495,10 +592,19 @@ __device__ void right_tri_mul(const TI *in, double *out, double *out2, int N, in
 // Returns sum_j log R_jj.
 // Phi and q2 are FP64 or FP32 storage; the Gram matrices, factors and tmp,
 // q1 are FP64.
-template <typename F>
-__device__ double cholqr(const F *Phi, double *tmp, double *q1, F *q2, double *Vout,
+// An FP64 block that is itself one of the outputs (q1 or q2) is factored in
+// place (MR: longest row held in registers).
+template <typename F, int MR = 8>
+__device__ __forceinline__ double cholqr(const F *Phi, double *tmp, double *q1, F *q2, double *Vout,
                          double *Vacc, int N, int m, Lds &L, Scalars *sc) {
   if (m == 0) { SYNC(); return 0.0; }
+  if constexpr (std::is_same<F, double>::value) {
+    if (q1 == Phi || q2 == Phi) {
+      double ld;
+      if (cholqr_inplace<MR>(const_cast<double *>(Phi), q1 == Phi ? q2 : q1, Vout, Vacc, N, m, L, sc, &ld))
+        return ld;
+    }
+  }
   bool shifted = false;
   // pass 1: Phi -> tmp
   gram(Phi, m, Phi, m, N, L.A, L.red);
