@@ -2012,9 +2012,101 @@ __device__ __forceinline__ void fock_propagate(const WalkerDesc &w, int sp, F *f
   }
 }
 
+// The column's checkerboard passes with the bonds of each thread held in
+// registers: bond TID + u * kThreads of colour c, packed as
+// i | j << 10 | coefficient index << 20 (or -1).  Valid for N <= 1024 (so a
+// colour, whose bonds are site-disjoint, has at most 2 kThreads bonds), at
+// most kFcol colours, and bond tables in LDS.
+constexpr int kFcol = 8;
+struct FockBonds {
+  int w[kFcol][2];
+};
+__device__ __forceinline__ bool fock_bonds(const WalkerDesc &w, const Lds &L, FockBonds &fb) {
+  if (!(L.bonds_ok && L.cs && w.N <= kFq * kThreads && w.ncol <= kFcol)) return false;
+  const BondSrc bs = bond_src(L, w);
+#pragma unroll
+  for (int c = 0; c < kFcol; ++c)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int v = -1;
+      if (c < w.ncol) {
+        const int b = bs.cs[c] + TID + u * kThreads;
+        if (b < bs.cs[c + 1]) {
+          const int ij = bs.bij[b];
+          v = (ij & 0xffff) | (int)(((unsigned)ij >> 16) << 10) | ((int)bs.bci[b] << 20);
+        }
+      }
+      fb.w[c][u] = v;
+    }
+  return true;
+}
+// one colour pass over the LDS column v (same arithmetic as colour_pass_t):
+// all loads first, stores only for real bonds
+template <typename P>
+__device__ __forceinline__ void fock_pass(const int (&wc)[2], P v, const lds_f64 *coef) {
+  using E = typename Elem<P>::T;
+  int i[2], j[2];
+  E xi[2], xj[2], d[2], o[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int a = wc[u] < 0 ? 0 : wc[u];
+    i[u] = a & 1023;
+    j[u] = (a >> 10) & 1023;
+    const int ci = a >> 20;
+    xi[u] = v[i[u]];
+    xj[u] = v[j[u]];
+    d[u] = (E)coef[2 * ci];
+    o[u] = (E)coef[2 * ci + 1];
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (wc[u] >= 0) {
+      v[i[u]] = d[u] * xi[u] + o[u] * xj[u];
+      v[j[u]] = o[u] * xi[u] + d[u] * xj[u];
+    }
+  lds_sync();
+}
+template <typename F>
+__device__ __forceinline__ void fock_propagate_cb(const WalkerDesc &w, int sp, F *fw, int l0, int l1,
+                                                  const double (&eps)[kFq], const Lds &L, const FockBonds &fb) {
+  const int N = w.N, ncol = w.ncol;
+  const double elam = w.elam, emlam = w.emlam;
+  const lds_f64 *coef = as_lds(L.bonds);
+  auto v = as_lds(fw);
+  int fc[kFq], fn[kFq];
+  auto fields = [&](int l, int (&f)[kFq]) {
+    const int8_t *srow = w.s + (size_t)(l - 1) * N;
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      const int i = TID + q * kThreads;
+      f[q] = i < N ? srow[i] : 1;
+    }
+  };
+  fields(l0, fc);
+  for (int l = l0; l <= l1; ++l) {
+    if (l < l1) fields(l + 1, fn);
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) {
+      const int i = TID + q * kThreads;
+      const int ss = sp == 0 ? fc[q] : -fc[q];
+      if (i < N) v[i] *= (F)((ss > 0 ? elam : emlam) * eps[q]);
+    }
+    lds_sync();
+    // E_K: colour ncol - 1 acts first
+#pragma unroll
+    for (int c = kFcol - 1; c >= 0; --c)
+      if (c < ncol) fock_pass(fb.w[c], v, coef);
+#pragma unroll
+    for (int q = 0; q < kFq; ++q) fc[q] = fn[q];
+  }
+}
+
 // returns accepted (uniform); *log_abs_r / *sign_r in scal.  F: storage of
 // the propagated column (FP32 for mixed-precision walkers); projections,
 // norms, the stored columns q_i and every ratio are FP64.
+// The Givens coefficients of the removal are kept in LDS as well (the last
+// two levels in uw, the current level of the addition in vec[6..7]) so that
+// the serial rotations of thread 0 read no device memory.
 template <typename F>
 __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc, bool commit,
                           Lds &L, F *fw, double *ratio_out) {
@@ -2029,7 +2121,10 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
   double *H = L.Ms0, *Mp = L.Ms1, *Mred = L.A;
   const int vs = L.vs;
   double *y = L.vec, *z = L.vec + vs, *vsum = L.vec + 2 * vs, *acol = L.vec + 3 * vs, *brow = L.vec + 4 * vs,
-         *tv = L.vec + 5 * vs;
+         *tv = L.vec + 5 * vs, *gcl = L.vec + 6 * vs, *gsl = L.vec + 7 * vs;
+  // removal coefficients of level lvl in LDS: cosines at uw + (lvl & 1) vs, sines 2 vs further
+  auto gcb = [&](int lvl) { return L.uw + (lvl & 1) * vs; };
+  auto gsb = [&](int lvl) { return L.uw + (2 + (lvl & 1)) * vs; };
   // scal[20] log_rne, [21] sign_rne, [22] zero flag, [23] log_rho
   if (TID == 0) { L.scal[20] = 0.0; L.scal[21] = 1.0; L.scal[22] = 0.0; L.scal[23] = 0.0; }
   SYNC();
@@ -2045,7 +2140,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     } else {
       for (int t = TID; t < ne * ne; t += kThreads) H[t] = V[t];
       SYNC();
-      const double *gc = fgc + (size_t)(lvl - 1) * mm, *gs = fgs + (size_t)(lvl - 1) * mm;
+      const double *gc = gcb(lvl - 1), *gs = gsb(lvl - 1);
       for (int r = k; r <= ne - 2; ++r) {
         const double cc = gc[r], ss = gs[r];
         for (int row = TID; row < ne; row += kThreads) {
@@ -2067,6 +2162,8 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         L.scal[25] = ss;
         gc[r] = cc;
         gs[r] = ss;
+        gcb(lvl)[r] = cc;
+        gsb(lvl)[r] = ss;
       }
       SYNC();
       const double cc = L.scal[24], ss = L.scal[25];
@@ -2094,7 +2191,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     double *Tm = L.B;
     for (int t = TID; t < ne * ne; t += kThreads) Tm[t] = w.Minv[sp][t];
     SYNC();
-    const double *gc = fgc + (size_t)(n - 1) * mm, *gs = fgs + (size_t)(n - 1) * mm;
+    const double *gc = gcb(n - 1), *gs = gsb(n - 1);
     for (int r = k; r <= ne - 2; ++r) {
       const double cc = gc[r], ss = gs[r];
       for (int col = TID; col < ne; col += kThreads) {
@@ -2125,6 +2222,8 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     SYNC();
     const bool fast = in_lds(fw) && N <= kFq * kThreads;
     const bool qcache = fast && ne <= kFne;
+    FockBonds fb;
+    const bool cb = fast && fock_bonds(w, L, fb);
     double eps_r[kFq];
 #pragma unroll
     for (int q = 0; q < kFq; ++q) {
@@ -2144,7 +2243,15 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
           for (int a = 0; a < kFne; ++a) qr[q][a] = (i < N && a < ne) ? Q[(size_t)i * ne + a] : 0.0;
         }
       }
-      if (fast) {
+      // this level's rotation coefficients, loaded under the propagation
+      double gcr = 0.0, gsr = 0.0;
+      if (TID < ne) {
+        gcr = fgc[(size_t)lvl * mm + TID];
+        gsr = fgs[(size_t)lvl * mm + TID];
+      }
+      if (cb) {
+        fock_propagate_cb(w, sp, fw, l0, l1, eps_r, L, fb);
+      } else if (fast) {
         fock_propagate(w, sp, fw, l0, l1, eps_r, L);
       } else {
         for (int l = l0; l <= l1; ++l) {
@@ -2152,7 +2259,11 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
           apply_ek(w, L, fw, 1);
         }
       }
-      const double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
+      if (TID < ne) {
+        gcl[TID] = gcr;
+        gsl[TID] = gsr;
+      }
+      const double *gc = gcl, *gs = gsl;
       for (int a = TID; a < vs; a += kThreads) vsum[a] = 0.0;
       SYNC();
       for (int pass = 0; pass < 2 && m > 0; ++pass) {
@@ -2247,7 +2358,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     const double *qn = fq + (size_t)(n - 1) * N;
     const int *occ = w.occ[sp];
     if (TID == 0) {
-      const double *gc = fgc + (size_t)(n - 1) * mm, *gs = fgs + (size_t)(n - 1) * mm;
+      const double *gc = gcb(n - 1), *gs = gsb(n - 1);
       for (int a = 0; a < ne; ++a) tv[a] = Qn[(size_t)j * ne + a];
       for (int r = k; r <= ne - 2; ++r) {
         const double a = tv[r], b = tv[r + 1];
@@ -2282,7 +2393,12 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       if (accepted && commit) {
         for (int lvl = 0; lvl < n; ++lvl) {
           double *Q = w.RQ[sp] + (size_t)lvl * N * ne;
-          const double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
+          if (TID < ne) {
+            gcl[TID] = fgc[(size_t)lvl * mm + TID];
+            gsl[TID] = fgs[(size_t)lvl * mm + TID];
+          }
+          SYNC();
+          const double *gc = gcl, *gs = gsl;
           const double *q = fq + (size_t)lvl * N;
           for (int i = TID; i < N; i += kThreads) {
             double *row = Q + (size_t)i * ne;
@@ -2303,6 +2419,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
             else if (a == ne - 1 && b == ne - 1) val = frho[lvl];
             V[t] = val;
           }
+          SYNC();
         }
         const double is = 1.0 / sch;
         double *Mi = w.Minv[sp];
