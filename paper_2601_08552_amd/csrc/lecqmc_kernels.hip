@@ -228,6 +228,23 @@ __device__ __forceinline__ BondSrc bond_src(const Lds &L, const WalkerDesc &w) {
   b.bci = (const lds_u8 *)(b.bij + w.nbonds);
   return b;
 }
+template <bool TL>
+__device__ __forceinline__ void bond_get_t(const WalkerDesc &w, const BondSrc &bs, int b, int &i, int &j, double &d,
+                                           double &o) {
+  if constexpr (TL) {
+    const int ij = bs.bij[b];
+    i = ij & 0xffff;
+    j = (int)((unsigned)ij >> 16);
+    const int ci = bs.bci[b];
+    d = bs.coef[2 * ci];
+    o = bs.coef[2 * ci + 1];
+  } else {
+    i = w.bi[b];
+    j = w.bj[b];
+    d = w.bdiag[b];
+    o = w.boff[b];
+  }
+}
 __device__ __forceinline__ void bond_get(const WalkerDesc &w, const BondSrc &bs, int b, int &i, int &j, double &d,
                                          double &o) {
   if (bs.lds) {
@@ -270,37 +287,34 @@ __device__ __forceinline__ int colour_begin(const WalkerDesc &w, const BondSrc &
   return bs.cs ? bs.cs[c] : w.col_start[c];
 }
 
-template <typename P>
-__device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc &bs, P X, int m, int c,
-                                              bool inverse) {
+template <bool TL, typename P>
+__device__ __forceinline__ void colour_pass_tt(const WalkerDesc &w, const BondSrc &bs, P X, int m, int b0, int b1,
+                                               bool inverse) {
   using E = typename Elem<P>::T;
-  const int b0 = colour_begin(w, bs, c), b1 = colour_begin(w, bs, c + 1);
   // thread = (bond slot, column): column fastest, so neighbouring lanes touch
   // neighbouring words of a row; one division per pass, 32-bit indices
   const int per = m > 0 ? kThreads / m : 0;
   const int col = m > 0 ? TID % m : 0, slot = m > 0 ? TID / m : kThreads;
   if (slot < per) {
     // four bonds per thread per round: all loads first, then all stores (the
-    // bonds of one colour are disjoint, so nothing aliases)
+    // bonds of one colour are disjoint, so nothing aliases).  A slot past the
+    // colour's end loads bond b0 again and stores nothing, so that no load
+    // waits behind a branch.
     for (int bb = b0 + slot; bb < b1; bb += 4 * per) {
       int ii[4], jj[4];
       E xi[4], xj[4], d[4], o[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int b = bb + u * per;
-        ii[u] = jj[u] = 0;
-        xi[u] = xj[u] = d[u] = o[u] = (E)0;
-        if (b < b1) {
-          int i, j;
-          double dd, oo;
-          bond_get(w, bs, b, i, j, dd, oo);
-          d[u] = (E)dd;
-          o[u] = (E)(inverse ? -oo : oo);
-          ii[u] = i * m + col;
-          jj[u] = j * m + col;
-          xi[u] = X[ii[u]];
-          xj[u] = X[jj[u]];
-        }
+        const int b = bb + u * per < b1 ? bb + u * per : b0;
+        int i, j;
+        double dd, oo;
+        bond_get_t<TL>(w, bs, b, i, j, dd, oo);
+        d[u] = (E)dd;
+        o[u] = (E)(inverse ? -oo : oo);
+        ii[u] = i * m + col;
+        jj[u] = j * m + col;
+        xi[u] = X[ii[u]];
+        xj[u] = X[jj[u]];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -312,17 +326,42 @@ __device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc
   }
   PassSync<P>::run();
 }
+template <typename P>
+__device__ __forceinline__ void colour_pass_t(const WalkerDesc &w, const BondSrc &bs, P X, int m, int c,
+                                              bool inverse) {
+  const int b0 = colour_begin(w, bs, c), b1 = colour_begin(w, bs, c + 1);
+  if (bs.lds) colour_pass_tt<true>(w, bs, X, m, b0, b1, inverse);
+  else colour_pass_tt<false>(w, bs, X, m, b0, b1, inverse);
+}
 
 template <typename P>
 __device__ __forceinline__ void diag_t(const WalkerDesc &w, P X, int m, int l, int sp, bool inverse) {
   using E = typename Elem<P>::T;
-  const int8_t *s = w.s + (size_t)(l - 1) * w.N;
-  for (int i = TID; i < w.N; i += kThreads) {
-    const int ss = sp == 0 ? s[i] : -s[i];
-    double f = (ss > 0 ? w.elam : w.emlam) * w.eps_fac[i];
-    if (inverse) f = 1.0 / f;
-    const E fe = (E)f;
-    for (int a = 0; a < m; ++a) X[(size_t)i * m + a] *= fe;
+  const int N = w.N;
+  const int8_t *s = w.s + (size_t)(l - 1) * N;
+  const double elam = w.elam, emlam = w.emlam;
+  // the fields and onsite factors of four rows are loaded before any row is scaled
+  constexpr int R = 4;
+  for (int i0 = TID; i0 < N; i0 += R * kThreads) {
+    int sv[R];
+    double ev[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = i0 + r * kThreads;
+      sv[r] = i < N ? s[i] : 1;
+      ev[r] = i < N ? w.eps_fac[i] : 1.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = i0 + r * kThreads;
+      if (i < N) {
+        const int ss = sp == 0 ? sv[r] : -sv[r];
+        double f = (ss > 0 ? elam : emlam) * ev[r];
+        if (inverse) f = 1.0 / f;
+        const E fe = (E)f;
+        for (int a = 0; a < m; ++a) X[(size_t)i * m + a] *= fe;
+      }
+    }
   }
   PassSync<P>::run();
 }

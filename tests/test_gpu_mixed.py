@@ -86,9 +86,10 @@ def test_mixed_trajectory_and_estimators(lq, ctx, name):
     assert sg == so
     assert np.array_equal(fg, fo) and np.array_equal(ug, uo) and np.array_equal(dg, do)
     st = g.stats()
-    assert st["logw_drift"] < 1e-4 and st["max_wrap_err"] < 1e-4
     lg, _ = g.tracked_weight()
     lo, _ = o.tracked_weight()
+    # the tracked-vs-fresh drift is an error of log|W| itself: same relative bar
+    assert st["logw_drift"] < LOGW_RTOL * max(1.0, abs(lo)) and st["max_wrap_err"] < 1e-4
     assert _rel(lg, lo) < LOGW_RTOL
     mg, mo = g.measure(), o.measure()
     assert np.max(np.abs(mg - mo)) < OBS_RTOL * max(1.0, np.max(np.abs(mo)))
