@@ -2079,64 +2079,74 @@ __device__ __forceinline__ bool fock_bonds(const WalkerDesc &w, const Lds &L, Fo
     }
   return true;
 }
-// one colour pass over the LDS column v (same arithmetic as colour_pass_t):
-// all loads first, stores only for real bonds
+// one colour pass over the LDS column v (same arithmetic as colour_pass_t),
+// without branches: a thread with no bond in a slot reads and writes its own
+// dummy word, so that every load is issued before the first store
 template <typename P>
-__device__ __forceinline__ void fock_pass(const int (&wc)[2], P v, const lds_f64 *coef) {
+__device__ __forceinline__ void fock_pass(const int (&wc)[2], P v, P dummy, const lds_f64 *coef) {
   using E = typename Elem<P>::T;
-  int i[2], j[2];
+  P pi[2], pj[2];
   E xi[2], xj[2], d[2], o[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const int a = wc[u] < 0 ? 0 : wc[u];
-    i[u] = a & 1023;
-    j[u] = (a >> 10) & 1023;
+    const bool ok = wc[u] >= 0;
+    const int a = ok ? wc[u] : 0;
+    pi[u] = ok ? v + (a & 1023) : dummy;
+    pj[u] = ok ? v + ((a >> 10) & 1023) : dummy;
     const int ci = a >> 20;
-    xi[u] = v[i[u]];
-    xj[u] = v[j[u]];
+    xi[u] = *pi[u];
+    xj[u] = *pj[u];
     d[u] = (E)coef[2 * ci];
     o[u] = (E)coef[2 * ci + 1];
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-    if (wc[u] >= 0) {
-      v[i[u]] = d[u] * xi[u] + o[u] * xj[u];
-      v[j[u]] = o[u] * xi[u] + d[u] * xj[u];
-    }
+  for (int u = 0; u < 2; ++u) {
+    *pi[u] = d[u] * xi[u] + o[u] * xj[u];
+    *pj[u] = o[u] * xi[u] + d[u] * xj[u];
+  }
   lds_sync();
 }
+// The fields of the level's slices (at most kFsl) for the thread's kFq sites
+// are read once, as bits (site q of slice l0 + t at bit kFq t + q).
+constexpr int kFsl = 16;
 template <typename F>
 __device__ __forceinline__ void fock_propagate_cb(const WalkerDesc &w, int sp, F *fw, int l0, int l1,
                                                   const double (&eps)[kFq], const Lds &L, const FockBonds &fb) {
-  const int N = w.N, ncol = w.ncol;
+  const int N = w.N, ncol = w.ncol, nsl = l1 - l0 + 1;
   const double elam = w.elam, emlam = w.emlam;
   const lds_f64 *coef = as_lds(L.bonds);
   auto v = as_lds(fw);
-  int fc[kFq], fn[kFq];
-  auto fields = [&](int l, int (&f)[kFq]) {
-    const int8_t *srow = w.s + (size_t)(l - 1) * N;
+  auto dummy = as_lds(reinterpret_cast<F *>(L.red + TID));
+  // every load is issued (rows and sites clamped into range) before any is used
+  int8_t f[kFsl][kFq];
+#pragma unroll
+  for (int t = 0; t < kFsl; ++t) {
+    const int8_t *srow = w.s + (size_t)(l0 - 1 + (t < nsl ? t : nsl - 1)) * N;
 #pragma unroll
     for (int q = 0; q < kFq; ++q) {
       const int i = TID + q * kThreads;
-      f[q] = i < N ? srow[i] : 1;
+      f[t][q] = srow[i < N ? i : 0];
     }
-  };
-  fields(l0, fc);
-  for (int l = l0; l <= l1; ++l) {
-    if (l < l1) fields(l + 1, fn);
+  }
+  unsigned long long bits = 0;
+#pragma unroll
+  for (int t = 0; t < kFsl; ++t)
+#pragma unroll
+    for (int q = 0; q < kFq; ++q)
+      if (t < nsl && TID + q * kThreads < N && f[t][q] > 0) bits |= 1ull << (kFq * t + q);
+  for (int t = 0; t < nsl; ++t) {
 #pragma unroll
     for (int q = 0; q < kFq; ++q) {
       const int i = TID + q * kThreads;
-      const int ss = sp == 0 ? fc[q] : -fc[q];
+      const bool up = (bits >> (kFq * t + q)) & 1ull;
+      const int ss = (sp == 0) == up ? 1 : -1;
       if (i < N) v[i] *= (F)((ss > 0 ? elam : emlam) * eps[q]);
     }
     lds_sync();
     // E_K: colour ncol - 1 acts first
 #pragma unroll
     for (int c = kFcol - 1; c >= 0; --c)
-      if (c < ncol) fock_pass(fb.w[c], v, coef);
-#pragma unroll
-    for (int q = 0; q < kFq; ++q) fc[q] = fn[q];
+      if (c < ncol) fock_pass(fb.w[c], v, dummy, coef);
   }
 }
 
@@ -2262,7 +2272,7 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     const bool fast = in_lds(fw) && N <= kFq * kThreads;
     const bool qcache = fast && ne <= kFne;
     FockBonds fb;
-    const bool cb = fast && fock_bonds(w, L, fb);
+    const bool cb = fast && w.nstab <= kFsl && fock_bonds(w, L, fb);
     double eps_r[kFq];
 #pragma unroll
     for (int q = 0; q < kFq; ++q) {
@@ -2334,7 +2344,38 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
         } else {
           gram(Q, ne, fw, 1, N, y, L.red);  // y = Q^T w
         }
-        if (TID == 0) {
+        if (TID == 0 && ne <= kFne) {
+          // the same steps on register copies (ne <= kFne): one LDS round trip
+          double yr[kFne], cr[kFne], sr[kFne];
+#pragma unroll
+          for (int a = 0; a < kFne; ++a) {
+            yr[a] = a < ne ? as_lds(y)[a] : 0.0;
+            cr[a] = a < ne ? as_lds(gc)[a] : 1.0;
+            sr[a] = a < ne ? as_lds(gs)[a] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < kFne - 1; ++r)
+            if (r >= k && r <= ne - 2) {
+              const double a = yr[r], b = yr[r + 1];
+              yr[r] = cr[r] * a + sr[r] * b;
+              yr[r + 1] = -sr[r] * a + cr[r] * b;
+            }
+#pragma unroll
+          for (int a = 0; a < kFne; ++a) {
+            yr[a] = a < m ? yr[a] : 0.0;
+            if (a < m) as_lds(vsum)[a] += yr[a];
+          }
+#pragma unroll
+          for (int r = kFne - 2; r >= 0; --r)
+            if (r >= k && r <= ne - 2) {
+              const double a = yr[r], b = yr[r + 1];
+              yr[r] = cr[r] * a - sr[r] * b;
+              yr[r + 1] = sr[r] * a + cr[r] * b;
+            }
+#pragma unroll
+          for (int a = 0; a < kFne; ++a)
+            if (a < ne) as_lds(z)[a] = yr[a];
+        } else if (TID == 0) {
           for (int r = k; r <= ne - 2; ++r) {
             const double a = y[r], b = y[r + 1];
             y[r] = gc[r] * a + gs[r] * b;
