@@ -801,6 +801,15 @@ __device__ __forceinline__ double halves_product(double v) {
   const double upper = __hiloint2double((int)b[1], (int)a[1]);
   return lower * upper;
 }
+// sum over all 64 lanes of a wave, the same bits in every lane (8 lanes,
+// then the 32-lane half, then the two halves)
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v = sum_ar(sum_bc(v));
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
 __device__ __forceinline__ double lane_read(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -2324,16 +2333,12 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
 #pragma unroll
           for (int q = 0; q < kFq; ++q) {
             const int i = TID + q * kThreads;
-            const double f = i < N ? (double)fw[i] : 0.0;
+            const double f = (double)as_lds(fw)[i < N ? i : 0];
 #pragma unroll
-            for (int a = 0; a < kFne; ++a) yp[a] += qr[q][a] * f;
+            for (int a = 0; a < kFne; ++a) yp[a] += qr[q][a] * (i < N ? f : 0.0);
           }
 #pragma unroll
-          for (int a = 0; a < kFne; ++a) {
-            double v = yp[a];
-            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-            yp[a] = v;
-          }
+          for (int a = 0; a < kFne; ++a) yp[a] = wave_sum_d(yp[a]);
           if ((TID & 63) == 0)
 #pragma unroll
             for (int a = 0; a < kFne; ++a) L.red[(TID >> 6) * kFne + a] = yp[a];
@@ -2411,7 +2416,14 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       }
       double nrm = 0.0;
       for (int i = TID; i < N; i += kThreads) nrm += (double)fw[i] * (double)fw[i];
-      nrm = sqrt(wg_sum(nrm, L.red));
+      {
+        // block sum: wave sums by DPP, then the four waves in a fixed order
+        nrm = wave_sum_d(nrm);
+        SYNC();
+        if ((TID & 63) == 0) L.red[TID >> 6] = nrm;
+        SYNC();
+        nrm = sqrt((L.red[0] + L.red[1]) + (L.red[2] + L.red[3]));
+      }
       if (!(nrm > 1e-300)) {
         if (TID == 0) L.scal[22] = 1.0;
         SYNC();
