@@ -2118,6 +2118,35 @@ __device__ __forceinline__ void fock_pass(const int (&wc)[2], P v, P dummy, cons
 // The fields of the level's slices (at most kFsl) for the thread's kFq sites
 // are read once, as bits (site q of slice l0 + t at bit kFq t + q).
 constexpr int kFsl = 16;
+// the first colour pass of a slice with the slice's diagonal factors folded
+// in: each end of a bond is scaled (as the diagonal pass scales it) before
+// the rotation; used when that colour's bonds cover every site once
+template <typename P>
+__device__ __forceinline__ void fock_pass_diag(const int (&wc)[2], P v, P dummy, const lds_f64 *coef,
+                                               const double (&fac)[4]) {
+  using E = typename Elem<P>::T;
+  P pi[2], pj[2];
+  E xi[2], xj[2], d[2], o[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const bool ok = wc[u] >= 0;
+    const int a = ok ? wc[u] : 0;
+    pi[u] = ok ? v + (a & 1023) : dummy;
+    pj[u] = ok ? v + ((a >> 10) & 1023) : dummy;
+    const int ci = a >> 20;
+    xi[u] = *pi[u];
+    xj[u] = *pj[u];
+    d[u] = (E)coef[2 * ci];
+    o[u] = (E)coef[2 * ci + 1];
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const E si = xi[u] * (E)fac[2 * u], sj = xj[u] * (E)fac[2 * u + 1];
+    *pi[u] = d[u] * si + o[u] * sj;
+    *pj[u] = o[u] * si + d[u] * sj;
+  }
+  lds_sync();
+}
 template <typename F>
 __device__ __forceinline__ void fock_propagate_cb(const WalkerDesc &w, int sp, F *fw, int l0, int l1,
                                                   const double (&eps)[kFq], const Lds &L, const FockBonds &fb) {
@@ -2126,6 +2155,59 @@ __device__ __forceinline__ void fock_propagate_cb(const WalkerDesc &w, int sp, F
   const lds_f64 *coef = as_lds(L.bonds);
   auto v = as_lds(fw);
   auto dummy = as_lds(reinterpret_cast<F *>(L.red + TID));
+  // The first colour's bonds cover every site once (N / 2 disjoint bonds):
+  // the diagonal factors are folded into that pass, taken at the four ends of
+  // the thread's two bonds of it.
+  if (N % 2 == 0 && L.cs[ncol] - L.cs[ncol - 1] == N / 2) {
+    int w0[2] = {-1, -1};   // the first colour's bond words (constant indices keep fb in registers)
+#pragma unroll
+    for (int c = 0; c < kFcol; ++c)
+      if (c == ncol - 1) {
+        w0[0] = fb.w[c][0];
+        w0[1] = fb.w[c][1];
+      }
+    int site[4];
+    bool real[4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool ok = w0[u] >= 0;
+      const int a = ok ? w0[u] : 0;
+      site[2 * u] = a & 1023;
+      site[2 * u + 1] = (a >> 10) & 1023;
+      real[2 * u] = real[2 * u + 1] = ok;
+    }
+    int8_t f[kFsl][4];
+    double epe[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) epe[e] = w.eps_fac[site[e]];
+#pragma unroll
+    for (int t = 0; t < kFsl; ++t) {
+      const int8_t *srow = w.s + (size_t)(l0 - 1 + (t < nsl ? t : nsl - 1)) * N;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f[t][e] = srow[site[e]];
+    }
+    unsigned long long bits = 0;
+#pragma unroll
+    for (int t = 0; t < kFsl; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (t < nsl && real[e] && f[t][e] > 0) bits |= 1ull << (4 * t + e);
+    for (int t = 0; t < nsl; ++t) {
+      double fac[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool up = (bits >> (4 * t + e)) & 1ull;
+        const int ss = (sp == 0) == up ? 1 : -1;
+        fac[e] = (ss > 0 ? elam : emlam) * epe[e];
+      }
+      // E_K: colour ncol - 1 acts first, with D folded in
+      fock_pass_diag(w0, v, dummy, coef, fac);
+#pragma unroll
+      for (int c = kFcol - 2; c >= 0; --c)
+        if (c < ncol - 1) fock_pass(fb.w[c], v, dummy, coef);
+    }
+    return;
+  }
   // every load is issued (rows and sites clamped into range) before any is used
   int8_t f[kFsl][kFq];
 #pragma unroll
