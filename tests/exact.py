@@ -169,8 +169,8 @@ class SectorED:
         n = self.n_up_site + self.n_dn_site
         return self.avg_diag(n[:, i] * n[:, j])
 
-    def hop_matrix_element(self, spin, i, j):
-        """<c_i^dag c_j> for spin 0 (up) / 1 (down) as a Fock-space matrix."""
+    def hop_single(self, spin, i, j):
+        """c_i^dag c_j of one spin species on that species' own sector basis."""
         basis = self.bu if spin == 0 else self.bd
         D = len(basis)
         index = {s: a for a, s in enumerate(basis)}
@@ -188,9 +188,35 @@ class SectorED:
                 sgn *= (-1) ** pos
                 new = tuple(sorted(lst + [i]))
                 M[index[new], a] += sgn
+        return M
+
+    def hop_matrix_element(self, spin, i, j):
+        """<c_i^dag c_j> for spin 0 (up) / 1 (down) as a Fock-space matrix."""
+        M = self.hop_single(spin, i, j)
         if spin == 0:
             return np.kron(M, np.eye(len(self.bd)))
         return np.kron(np.eye(len(self.bu)), M)
+
+    def avg_kron(self, Pu, Qd):
+        """<O> for O = Pu (x) Qd (up factor, down factor) without forming O."""
+        Du, Dd = len(self.bu), len(self.bd)
+        TL4 = self.TL.reshape(Du, Dd, Du, Dd)
+        return float(np.einsum("ac,bd,cdab->", Pu, Qd, TL4) / self.Z)
+
+    def transverse_sum(self, rows, cols):
+        """sum over i in rows, j in cols of <S^x_i S^x_j + S^y_i S^y_j>
+        = (1/2) <S+_i S-_j + S-_i S+_j>, with the spin-flip products written
+        per species: S+_i S-_j = (c_iu^dag c_ju) (x) (delta_ij - c_jd^dag c_id)
+        and S-_i S+_j = (delta_ij - c_ju^dag c_iu) (x) (c_id^dag c_jd)."""
+        Iu, Id = np.eye(len(self.bu)), np.eye(len(self.bd))
+        tot = 0.0
+        for i in rows:
+            for j in cols:
+                d = 1.0 if i == j else 0.0
+                pm = self.avg_kron(self.hop_single(0, i, j), d * Id - self.hop_single(1, j, i))
+                mp = self.avg_kron(d * Iu - self.hop_single(0, j, i), self.hop_single(1, i, j))
+                tot += 0.5 * (pm + mp)
+        return tot
 
     def ekin_per_site(self):
         tot = 0.0

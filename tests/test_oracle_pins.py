@@ -311,6 +311,12 @@ def test_mc_hubbard_against_trotter_ed():
         ref = ed.szz(i, j) + ed.spsm(i, j)
         _check(bins, off_ss + i * N + j, ref)
         _check(bins, off_ss + N * N + i * N + j, ed.nn(i, j))
+    # S_par(q=0) = (1/L) sum_ij <SxSx + SySy> (main text, definition beside
+    # Fig. 4(a)): the total [4] and its one-sublattice block [8 + ns^2]
+    spar = ed.transverse_sum(range(N), range(N)) / N
+    assert spar > 0.05   # far from zero, so a wrong normalisation shows
+    _check(bins, 4, spar)
+    _check(bins, 8 + 1, spar)
 
 
 def test_mc_ed_benchmark_point_short():
@@ -417,6 +423,38 @@ def test_mc_flat_band_against_trotter_ed():
     _check(bins, 8 + 0, ref11)
     _check(bins, 8 + 1, ref12)
     _check(bins, 3, ed.ekin_per_site())
+    # sublattice-resolved S_par(q=0)_ab = (1/L_c) sum_{i in a, j in b}
+    # <SxSx + SySy> and its total (L_c = 4 cells)
+    sub = [list(range(0, 8, 2)), list(range(1, 8, 2))]
+    for a in range(2):
+        for b in range(2):
+            _check(bins, 8 + 4 + 2 * a + b, ed.transverse_sum(sub[a], sub[b]) / 4)
+    _check(bins, 4, ed.transverse_sum(range(8), range(8)) / 4)
     # S^z_tot = 0 sector: sum_ab S^zz_ab(q=0) vanishes configuration by configuration
     tot = bins[:, 8:12].sum(axis=1)
     assert np.max(np.abs(tot)) < 1e-9
+
+
+def test_ed_transverse_sum_one_electron():
+    """The ED transverse sum itself: one up electron has S = S^z = 1/2, so
+    <S_x^2 + S_y^2> = S(S+1) - (S^z)^2 = 1/2 at any temperature."""
+    lat = W.periodic_chain(6)
+    par = W.Params(U=4.0, beta=1.0, dtau=0.1, n_stab=5, n_up=1, n_dn=0)
+    ed = exact.SectorED(lat, par)
+    assert abs(ed.transverse_sum(range(6), range(6)) - 0.5) < 1e-12
+
+
+def test_szz_total_sum_rule_with_imbalance():
+    """S^z_tot = (N_up - N_dn)/2 = M in every configuration, so the total
+    S^zz(q=0) = (1/L_c) <(S^z_tot)^2> and the sum of its sublattice blocks are
+    M^2 / L_c per sample (Fig. 4 caption, sum rule); S_par(q=0) against ED."""
+    lat = W.flat_band_chain(4, -0.2, 1.0, 1.0, -0.2)
+    par = W.Params(U=2.0, beta=1.0, dtau=0.1, n_stab=5, n_up=3, n_dn=1, seed=6)
+    w = oracle.Walker(lat, par)
+    bins = _run_bins(w, 16, 30, 10)
+    M, Lc = 1.0, 4
+    for b in bins:
+        assert abs(b[5] - b[0] * M * M / Lc) < 1e-9 * max(1.0, abs(b[0]))
+        assert abs(b[8:12].sum() - b[0] * M * M / Lc) < 1e-9 * max(1.0, abs(b[0]))
+    ed = exact.SectorED(lat, par)
+    _check(bins, 4, ed.transverse_sum(range(8), range(8)) / Lc)
