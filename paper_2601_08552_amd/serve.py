@@ -275,6 +275,11 @@ class LaneServer:
                 with self.lock:
                     self.updates += n
                 self._retire(ln, clock())
+            # retired walkers still count against the shared budget, and only
+            # this thread may free them (they belong to this lane's context):
+            # free them before leaving, or a lane still waiting for memory
+            # would wait forever
+            self._free(ln)
         except BaseException as exc:    # reported by run() on the caller's thread
             errors.append(exc)
 

@@ -147,3 +147,27 @@ def test_lanes_keep_the_budget(monkeypatch):
     rep = srv.run(reqs)
     assert rep["requests"] == len(reqs) and _Walker.live == 0
     assert 0 < peak["mem"] <= budget
+
+
+def test_lane_leaving_frees_its_retired_walkers(monkeypatch):
+    """A lane whose requests are all done must free its retired walkers when
+    its thread leaves: here the cheap request's walker (1000 of a 1500
+    budget) would otherwise block the expensive request of the other lane
+    for good."""
+    import threading
+    from paper_2601_08552_amd import workloads as W
+    monkeypatch.setattr(serve.lecqmc, "Walker", _LaneWalker)
+    monkeypatch.setattr(serve.lecqmc, "sweep_batch", _lane_sweep)
+    monkeypatch.setattr(serve.lecqmc, "footprint_bytes", lambda lat, par: 1000)
+    _Walker.live = 0
+    par = W.Params(U=2.0, beta=0.5, dtau=0.05, n_stab=10, n_up=1, n_dn=1, seed=1)
+    cheap = serve.Request(0, W.square_lattice(4), par, 2, 0.0)
+    dear = serve.Request(1, W.square_lattice(48), par, 2, 0.2)
+    srv = serve.LaneServer([_LaneCtx(0.001), _LaneCtx(0.002)], budget_bytes=1500, edges=(1e-3,))
+    assert srv.lane_of(cheap) == 0 and srv.lane_of(dear) == 1
+    out = {}
+    th = threading.Thread(target=lambda: out.setdefault("rep", srv.run([cheap, dear])), daemon=True)
+    th.start()
+    th.join(timeout=20.0)
+    assert not th.is_alive(), f"server hung: in_use={srv.in_use}, graveyards={[len(l['graveyard']) for l in srv.lanes]}"
+    assert out["rep"]["requests"] == 2 and srv.in_use == 0 and _Walker.live == 0
