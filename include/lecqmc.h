@@ -45,7 +45,9 @@ extern "C" {
 #define LECQMC_OK 0
 #define LECQMC_EINVAL (-1)    /* bad sizes or arguments (message says which)          */
 #define LECQMC_ENOMEM (-2)    /* device footprint over the context budget (refused)   */
-#define LECQMC_EUNSTABLE (-3) /* QR breakdown or wrap error above wrap_tol; walker stays valid */
+#define LECQMC_EUNSTABLE (-3) /* singular inverse or QR breakdown (kept), or a wrap error above
+                                 wrap_tol on a measuring sweep (reported once by the next
+                                 call that reads the walker's status; the walker stays valid) */
 #define LECQMC_EDEVICE (-4)   /* HIP runtime error                                    */
 #define LECQMC_ESTATE (-5)    /* call not valid in the walker's state                 */
 
@@ -60,6 +62,11 @@ extern "C" {
 #define LECQMC_NO_FLIPS 2     /* flags: skip the Ising flips (fields frozen)          */
 
 #define LECQMC_MAX_NE 256     /* largest particle number per spin handled on device  */
+
+/* Flags not provided: a symmetric checkerboard split (e^{-dtau K/2} on both
+ * sides of D_l) and heat-bath acceptance.  The paper fixes neither; the
+ * build implements one reading of each (asymmetric product, Metropolis on
+ * |r|), the one its oracle pins. */
 
 typedef struct lecqmc_ctx lecqmc_ctx;
 typedef struct lecqmc_walker lecqmc_walker;
@@ -81,7 +88,11 @@ typedef struct {
   uint64_t seed, walker_id; /* key of the counter-based generator             */
   int32_t precision;        /* LECQMC_FP64 or LECQMC_MIXED                    */
   int32_t flags;            /* LECQMC_NO_FOCK | LECQMC_NO_FLIPS               */
-  double wrap_tol;          /* max |A_wrap - A_fresh| diagonal (<= 0: 1e-8)   */
+  double wrap_tol;          /* largest |A_wrap - A_fresh| on the diagonal at a
+                               measured stabilisation boundary (SM Sec. I.A: the
+                               wrapped and the freshly recomputed Green's
+                               functions agree); <= 0: 1e-8 (FP64) or 1e-4
+                               (LECQMC_MIXED)                                   */
 } lecqmc_params;
 
 typedef struct {
@@ -118,7 +129,9 @@ int lecqmc_ctx_phase_times(lecqmc_ctx *ctx, double ms[3], int64_t counts[3]);
  * input is invalid. */
 size_t lecqmc_footprint_bytes(const lecqmc_lattice *lat, const lecqmc_params *par);
 
-/* Create a walker: copies the lattice, builds the model tables, draws the
+/* Create a walker (one Markov chain over (eta, s), main text Eq. (1)):
+ * copies the lattice, builds the model tables (checkerboard bond
+ * exponentials; Ising decoupling cosh(lambda) = exp(dtau U / 2)), draws the
  * fields (fields_or_null == NULL: s = +1 iff U(INIT_FIELD) < 1/2) and the
  * occupation (NULL: partial Fisher-Yates shuffle) or takes the given ones,
  * fields [L_tau][n_sites] int8 (+-1), occupations int32 distinct sites in
@@ -128,12 +141,21 @@ int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, const lecqm
                          const int32_t *occ_dn_or_null, lecqmc_walker **out);
 int lecqmc_destroy_walker(lecqmc_walker *w);
 
-/* n_sweeps full sweeps; do_measure != 0 accumulates estimators at the
- * interior stabilisation boundaries (tau = beta when there is one block). */
+/* n_sweeps full sweeps (left stack, forward pass with the Ising-field
+ * updates by the fast update of the projector-like sweep, main text
+ * "Ensemble constrained quantum Monte Carlo"; QR every n_stab slices, SM
+ * Sec. I.A; N_sigma particle-hole swaps per spin, main text "Linear ensemble
+ * constrained quantum Monte Carlo", SM Secs. I.A and I.B).  do_measure != 0
+ * accumulates estimators at the interior stabilisation boundaries (tau =
+ * beta when there is one block) and runs the wrap check against wrap_tol.
+ * Returns without waiting: device errors and LECQMC_EUNSTABLE surface on the
+ * next call that reads the walker back. */
 int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measure);
 /* The same for n walkers of one context in one launch per phase; shapes
  * may differ between walkers.  FP64 and mixed-precision walkers may be
- * combined: each precision gets its own launch per phase. */
+ * combined: each precision gets its own launch per phase.  ws holds n
+ * distinct walkers (LECQMC_EINVAL if one appears twice).  The descriptor
+ * array is grown with hipMalloc when n exceeds every earlier call's. */
 int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure);
 
 /* A fixed batch of walkers of one context (uneven shapes and precisions
@@ -176,14 +198,18 @@ int lecqmc_set_shape(lecqmc_walker *w, int32_t tile, int32_t chunk);
 int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *tile_out, int32_t *chunk_out,
                     double *fwd_ms_out);
 
-/* Fresh log|W| and sign from the current (eta, s) (right chain + QR, FP64
- * whatever the walker's precision). */
+/* Fresh log|W| and sign from the current (eta, s), main text Eq. (1): the
+ * right chain B_s(beta, 0) P with a QR every n_stab slices (SM Sec. I.A,
+ * B_i Q_{i-1} = Q_i V_i), log|W| = sum log V_jj + log|det(P^T Q_n)| summed
+ * over both spins; FP64 whatever the walker's precision. */
 int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);
 /* Weight carried by the chain (updated by every accepted move, reset to the
  * fresh value at tau = beta of each sweep). */
 int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);
 
-/* Sign-weighted accumulators since the last reset; layout:
+/* Sign-weighted accumulators since the last reset (Wick contractions of
+ * A = Phi_R (Phi_L Phi_R)^{-1} Phi_L at the measurement boundaries; the q = 0
+ * structure factors as defined with main text Fig. 4); layout:
  *  [0] sum sign  [1] number of measurements  [2] double occupancy per site
  *  [3] kinetic energy per site  [4] S_par(q=0) = (1/L_c) sum_ij <SxSx+SySy>
  *  [5] S_zz(q=0) total  [6] onsite energy per site  [7] density per site
@@ -192,6 +218,10 @@ int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign);
  * every entry already multiplied by the sign of the configuration. */
 int64_t lecqmc_obs_size(const lecqmc_walker *w);
 int lecqmc_measure(lecqmc_walker *w, double *out, int64_t n);
+/* Status-reading calls (lecqmc_measure, lecqmc_get_stats, lecqmc_log_weight,
+ * lecqmc_tracked_weight and the parity surface) fill their outputs and then
+ * return LECQMC_EUNSTABLE when a sweep since the last report found a wrap
+ * error above wrap_tol (or a singular inverse). */
 int lecqmc_reset_measure(lecqmc_walker *w);
 int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st);
 
@@ -202,12 +232,22 @@ int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const int32_t *occ_
                      const int32_t *occ_dn, uint64_t sweep_counter);
 
 /* Parity surface (fresh recomputation, small systems):
- * G_ij = <c_i c_j^dag> at slice boundary b in 0..L_tau, N x N row-major. */
+ * G_ij = <c_i c_j^dag> at slice boundary b in 0..L_tau, N x N row-major,
+ * G = I - Phi_R (Phi_L Phi_R)^{-1} Phi_L with Phi_R = B_s(b, 0) P and
+ * Phi_L = P^T B_s(beta, b), both stabilised by QR (SM Sec. I.A).  The N x N
+ * device staging is allocated for the call only and counts against the
+ * context's budget while it lives (LECQMC_ENOMEM if it does not fit). */
 int lecqmc_green(lecqmc_walker *w, int32_t boundary, int32_t spin, double *G);
-/* r = r_up r_dn for flipping s_{slice, site} (slice 0-based), not applied. */
+/* r = r_up r_dn for flipping s_{slice, site} (slice 0-based), not applied:
+ * r_sigma = 1 + Delta_sigma [Phi_R M^{-1} Phi_L]_{site, site} at the flip
+ * point of the slice (the fast-update ratio, main text "Ensemble constrained
+ * quantum Monte Carlo"). */
 int lecqmc_flip_ratio(lecqmc_walker *w, int32_t slice, int32_t site, double *ratio);
 /* Remove occupied index k_index of spin, add empty site j: weight ratio of the
- * composite move from a fresh right stack, not applied. */
+ * composite move (removal by column permutation and Givens retriangulation,
+ * SM Sec. I.B; addition by one-column propagation and Gram-Schmidt at every
+ * level, SM Sec. I.A and main text eq. ratio) from a fresh right stack, not
+ * applied. */
 int lecqmc_swap_ratio(lecqmc_walker *w, int32_t spin, int32_t k_index, int32_t j_site, double *ratio);
 
 const char *lecqmc_last_error(void);

@@ -92,7 +92,6 @@ struct lecqmc_walker {
   WalkerDesc *d_desc;    // device copy
   void *dmem;
   size_t bytes;
-  double *d_green;
   int N, L, nblk, ne[2], mmax, nobs;
   int batches;           // live lecqmc_batch objects that hold this walker
 };
@@ -439,10 +438,22 @@ extern "C" int lecqmc_ctx_phase_times(lecqmc_ctx *c, double ms[3], int64_t count
 // ---------------------------------------------------------------------------
 // walker
 // ---------------------------------------------------------------------------
-static int check_status(lecqmc_walker *w) {
+// Status of the walker's last kernels: a singular inverse or QR breakdown
+// (bit 2, kept: the chain's numbers are no longer trusted) or a wrap error
+// above wrap_tol on a measuring sweep (bit 3, cleared once reported: the
+// walker stays valid and the caller may lower n_stab).  sc_out (if set)
+// receives the scalars read.
+static int check_status(lecqmc_walker *w, Scalars *sc_out = nullptr) {
   Scalars sc;
   HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  if (sc_out) *sc_out = sc;
   if (sc.status & 4) return fail(LECQMC_EUNSTABLE, "singular P^T B P or QR breakdown");
+  if (sc.status & 8) {
+    const int st = sc.status & ~8;
+    HIPCHK(xfer(w->ctx, &w->h.sc->status, &st, sizeof st, hipMemcpyHostToDevice));
+    return fail(LECQMC_EUNSTABLE, "wrap error %.3e of the last measuring sweep above wrap_tol %.3e",
+                sc.wrap_sweep, w->h.wrap_tol);
+  }
   return 0;
 }
 
@@ -477,7 +488,6 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   w->ctx = ctx;
   w->dmem = dmem;
   w->bytes = p.total;
-  w->d_green = nullptr;
   w->N = N;
   w->L = L;
   w->nblk = (L + par->n_stab - 1) / par->n_stab;
@@ -509,7 +519,8 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   d.emlam = exp(-lambda);
   d.delta_dn_s = exp(-2.0 * lambda) - 1.0;   // sigma * s = +1 flipped to -1
   d.delta_up_s = exp(2.0 * lambda) - 1.0;    // sigma * s = -1 flipped to +1
-  d.wrap_tol = par->wrap_tol > 0 ? par->wrap_tol : 1e-8;
+  // default tolerance of the wrap check: FP64 rounding, or FP32 propagation
+  d.wrap_tol = par->wrap_tol > 0 ? par->wrap_tol : (d.mixed ? 1e-4 : 1e-8);
   d.sc = (Scalars *)(base + p.off_sc);
   d.s = (int8_t *)(base + p.off_s);
   for (int s = 0; s < 2; ++s) {
@@ -643,7 +654,6 @@ extern "C" int lecqmc_destroy_walker(lecqmc_walker *w) {
   if (w->batches > 0) return fail(LECQMC_ESTATE, "walker still belongs to %d batch(es)", w->batches);
   (void)hipSetDevice(w->ctx->device);
   (void)hipStreamSynchronize(w->ctx->stream);
-  if (w->d_green) (void)hipFree(w->d_green);
   (void)hipFree(w->dmem);
   w->ctx->used -= w->bytes;
   w->ctx->live_walkers -= 1;
@@ -666,22 +676,76 @@ extern "C" int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measu
   return 0;
 }
 
-extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure) {
-  if (!ws || n <= 0 || n_sweeps < 0) return fail(LECQMC_EINVAL, "bad arguments");
+// Walkers of a batch call in launch order (FP64 first, then mixed precision),
+// after the checks both batch entry points share.
+static int batch_order(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, std::vector<lecqmc_walker *> &order,
+                       int *n64) {
+  if (!ws || n <= 0 || n_sweeps < 0 || !ws[0]) return fail(LECQMC_EINVAL, "bad arguments");
   lecqmc_ctx *c = ws[0]->ctx;
-  // FP64 walkers first, then mixed-precision ones: one launch per group and phase
-  std::vector<lecqmc_walker *> order;
+  order.clear();
   for (int pass = 0; pass < 2; ++pass)
     for (int t = 0; t < n; ++t) {
       if (!ws[t] || ws[t]->ctx != c) return fail(LECQMC_EINVAL, "walkers of a batch must share one context");
       if (ws[t]->h.mixed == pass) order.push_back(ws[t]);
     }
-  std::vector<WalkerDesc> hd(n);
-  int n64 = 0;
-  for (int t = 0; t < n; ++t) {
-    hd[t] = order[t]->h;
-    n64 += order[t]->h.mixed ? 0 : 1;
+  {
+    // two workgroups of every phase would update one walker's state at once
+    std::vector<lecqmc_walker *> sorted(order);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(LECQMC_EINVAL, "a walker appears twice in the batch");
   }
+  *n64 = 0;
+  for (lecqmc_walker *w : order) *n64 += w->h.mixed ? 0 : 1;
+  return 0;
+}
+
+// Upload the descriptors of `order` to d (device) and run the sweeps, one
+// launch per precision group and phase.  timing: record phase events.
+static int batch_run(lecqmc_ctx *c, const std::vector<lecqmc_walker *> &order, int n64, WalkerDesc *d,
+                     int32_t n_sweeps, int32_t do_measure, bool timing) {
+  const int n = (int)order.size();
+  std::vector<WalkerDesc> hd(n);
+  for (int t = 0; t < n; ++t) hd[t] = order[t]->h;
+  struct Group {
+    const WalkerDesc *d;
+    int n;
+    LaunchCfg cf;
+  };
+  std::vector<Group> groups;
+  if (n64 > 0) groups.push_back({d, n64, launch_cfg(order.data(), n64)});
+  if (n > n64) groups.push_back({d + n64, n - n64, launch_cfg(order.data() + n64, n - n64)});
+  for (const Group &g : groups)
+    if (!g.cf.fits) return fail(LECQMC_EINVAL, "the chain staging of these walkers does not fit one launch's LDS; "
+                                               "sweep them in separate batches or give them smaller chunks");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(xfer(c, d, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
+  auto each = [&](auto &&launch) {
+    for (const Group &g : groups) {
+      const hipError_t e = launch(g);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  auto phase = [&](int ph, auto &&launch) { return timing ? timed(c, ph, launch) : launch(); };
+  for (int t = 0; t < n_sweeps; ++t) {
+    HIPCHK(phase(0, [&] { return each([&](const Group &g) {
+      return launch_left_stack(g.d, g.n, g.cf.left, g.cf.mixed, c->stream); }); }));
+    HIPCHK(phase(1, [&] { return each([&](const Group &g) {
+      return launch_forward(g.d, g.n, g.cf.fwd, g.cf.tile, do_measure, g.cf.mixed, c->stream); }); }));
+    if (do_measure)
+      HIPCHK(each([&](const Group &g) { return launch_measure(g.d, g.n, g.cf.slots, g.cf.meas, c->stream); }));
+    HIPCHK(phase(2, [&] { return each([&](const Group &g) {
+      return launch_fock(g.d, g.n, g.cf.fock, g.cf.mixed, c->stream); }); }));
+  }
+  return 0;
+}
+
+extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure) {
+  std::vector<lecqmc_walker *> order;
+  int n64 = 0;
+  if (int rc = batch_order(ws, n, n_sweeps, order, &n64)) return rc;
+  lecqmc_ctx *c = order[0]->ctx;
   HIPCHK(hipSetDevice(c->device));
   if (c->batch_cap < n) {
     const int cap = std::max(n, std::max(64, 2 * c->batch_cap));
@@ -692,37 +756,7 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
     c->d_batch = nd;
     c->batch_cap = cap;
   }
-  HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(xfer(c, c->d_batch, hd.data(), sizeof(WalkerDesc) * n, hipMemcpyHostToDevice));
-  struct Group {
-    const WalkerDesc *d;
-    int n;
-    LaunchCfg cf;
-  };
-  std::vector<Group> groups;
-  if (n64 > 0) groups.push_back({c->d_batch, n64, launch_cfg(order.data(), n64)});
-  if (n > n64) groups.push_back({c->d_batch + n64, n - n64, launch_cfg(order.data() + n64, n - n64)});
-  for (const Group &g : groups)
-    if (!g.cf.fits) return fail(LECQMC_EINVAL, "the chain staging of these walkers does not fit one launch's LDS; "
-                                               "sweep them in separate batches or give them smaller chunks");
-  auto each = [&](auto &&launch) {
-    for (const Group &g : groups) {
-      const hipError_t e = launch(g);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
-  for (int t = 0; t < n_sweeps; ++t) {
-    HIPCHK(timed(c, 0, [&] { return each([&](const Group &g) {
-      return launch_left_stack(g.d, g.n, g.cf.left, g.cf.mixed, c->stream); }); }));
-    HIPCHK(timed(c, 1, [&] { return each([&](const Group &g) {
-      return launch_forward(g.d, g.n, g.cf.fwd, g.cf.tile, do_measure, g.cf.mixed, c->stream); }); }));
-    if (do_measure)
-      HIPCHK(each([&](const Group &g) { return launch_measure(g.d, g.n, g.cf.slots, g.cf.meas, c->stream); }));
-    HIPCHK(timed(c, 2, [&] { return each([&](const Group &g) {
-      return launch_fock(g.d, g.n, g.cf.fock, g.cf.mixed, c->stream); }); }));
-  }
-  return 0;
+  return batch_run(c, order, n64, c->d_batch, n_sweeps, do_measure, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -970,10 +1004,10 @@ extern "C" int lecqmc_log_weight(lecqmc_walker *w, double *log_abs_w, int32_t *s
   HIPCHK(launch_fresh_weight(w->d_desc, 1, cf.fresh, 0, w->ctx->stream));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
-  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  const int rc = check_status(w, &sc);
   *log_abs_w = sc.fresh_logw;
   *sign = sc.fresh_sign;
-  return (sc.status & 4) ? fail(LECQMC_EUNSTABLE, "singular P^T B P") : 0;
+  return rc;
 }
 
 extern "C" int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_t *sign) {
@@ -981,10 +1015,10 @@ extern "C" int lecqmc_tracked_weight(lecqmc_walker *w, double *log_abs_w, int32_
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
-  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  const int rc = check_status(w, &sc);
   *log_abs_w = sc.logw + sc.fock_logw[0] + sc.fock_logw[1];
   *sign = sc.sign * sc.fock_sign[0] * sc.fock_sign[1];
-  return 0;
+  return rc;
 }
 
 extern "C" int64_t lecqmc_obs_size(const lecqmc_walker *w) { return w ? w->nobs : 0; }
@@ -994,7 +1028,7 @@ extern "C" int lecqmc_measure(lecqmc_walker *w, double *out, int64_t n) {
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   HIPCHK(xfer(w->ctx, out, w->h.obs, sizeof(double) * w->nobs, hipMemcpyDeviceToHost));
-  return 0;
+  return check_status(w);
 }
 
 extern "C" int lecqmc_reset_measure(lecqmc_walker *w) {
@@ -1010,7 +1044,8 @@ extern "C" int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st) {
   HIPCHK(hipSetDevice(w->ctx->device));
   HIPCHK(hipStreamSynchronize(w->ctx->stream));
   Scalars sc;
-  HIPCHK(xfer(w->ctx, &sc, w->h.sc, sizeof sc, hipMemcpyDeviceToHost));
+  const int rc = check_status(w, &sc);
+  if (rc == LECQMC_EDEVICE) return rc;
   st->flip_attempts = sc.flip_att;
   st->flip_accepts = sc.flip_acc;
   st->swap_attempts = sc.swap_att[0] + sc.swap_att[1];
@@ -1019,7 +1054,7 @@ extern "C" int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st) {
   st->logw_drift = sc.logw_drift;
   st->qr_shifted = sc.qr_shifted;
   st->sweeps = sc.sweep;
-  return 0;
+  return rc;
 }
 
 extern "C" int lecqmc_get_state(lecqmc_walker *w, int8_t *fields, int32_t *occ_up, int32_t *occ_dn,
@@ -1072,11 +1107,22 @@ extern "C" int lecqmc_set_state(lecqmc_walker *w, const int8_t *fields, const in
 extern "C" int lecqmc_green(lecqmc_walker *w, int32_t boundary, int32_t spin, double *G) {
   if (!w || !G || boundary < 0 || boundary > w->L || spin < 0 || spin > 1) return fail(LECQMC_EINVAL, "bad arguments");
   if (w->N > 8192) return fail(LECQMC_EINVAL, "green: N x N output limited to N <= 8192");
-  HIPCHK(hipSetDevice(w->ctx->device));
-  if (!w->d_green) HIPCHK(hipMalloc(&w->d_green, sizeof(double) * (size_t)w->N * w->N));
-  HIPCHK(launch_green(w->d_desc, w->mmax, boundary, spin, w->d_green, w->ctx->stream));
-  HIPCHK(hipStreamSynchronize(w->ctx->stream));
-  HIPCHK(xfer(w->ctx, G, w->d_green, sizeof(double) * (size_t)w->N * w->N, hipMemcpyDeviceToHost));
+  // the N x N staging buffer lives for this call only and counts against
+  // the context's budget while it does
+  lecqmc_ctx *c = w->ctx;
+  const size_t bytes = sizeof(double) * (size_t)w->N * w->N;
+  if (c->budget && c->used + bytes > c->budget)
+    return fail(LECQMC_ENOMEM, "green: %zu bytes of staging, %zu of %zu in use", bytes, c->used, c->budget);
+  HIPCHK(hipSetDevice(c->device));
+  double *dg = nullptr;
+  HIPCHK(hipMalloc(&dg, bytes));
+  c->used += bytes;
+  hipError_t e = launch_green(w->d_desc, w->mmax, boundary, spin, dg, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = xfer(c, G, dg, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(dg);
+  c->used -= bytes;
+  if (e != hipSuccess) return fail(LECQMC_EDEVICE, "green: %s", hipGetErrorString(e));
   return check_status(w);
 }
 

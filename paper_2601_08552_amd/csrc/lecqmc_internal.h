@@ -20,7 +20,8 @@ struct Scalars {
   unsigned long long sweep;     // completed sweeps
   double logw;                  // tracked log|W| (up to the pending Fock terms below)
   int sign;                     // tracked sign
-  int status;                   // 0 ok, bit 1 = QR shift used, bit 2 = singular inverse
+  int status;                   // 0 ok, bit 1 = QR shift used, bit 2 = singular inverse or QR
+                                // breakdown, bit 3 = wrap error of a measuring sweep above wrap_tol
   long long flip_att, flip_acc, qr_shifted;
   long long swap_att[2], swap_acc[2];   // per spin (one Fock workgroup per spin)
   double fock_logw[2];          // log|r| of accepted swaps per spin, folded in by the next forward pass
@@ -29,6 +30,7 @@ struct Scalars {
   double fresh_logw;            // written by the fresh-weight kernel
   int fresh_sign;
   int pad;
+  double wrap_sweep;            // largest wrap error of the last measuring sweep
   long long fwd_ticks;          // wall-clock ticks of the last forward pass of this walker
   double dbg[4];
 };

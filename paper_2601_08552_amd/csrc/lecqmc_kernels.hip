@@ -2003,9 +2003,13 @@ __global__ void __launch_bounds__(kThreads) k_measure_sum(const WalkerDesc *__re
     w.obs[t] = s;
   }
   if (TID == 0) {
-    double mx = w.sc->max_wrap;
-    for (int q = 0; q < slots; ++q) mx = fmax(mx, w.mpart[(size_t)q * rec + w.nobs]);
-    w.sc->max_wrap = mx;
+    // wrap-versus-fresh check of the stabilisation (SM Sec. I.A): the largest
+    // diagonal difference of this sweep's boundaries against the tolerance
+    double sw = 0.0;
+    for (int q = 0; q < slots; ++q) sw = fmax(sw, w.mpart[(size_t)q * rec + w.nobs]);
+    w.sc->max_wrap = fmax(w.sc->max_wrap, sw);
+    w.sc->wrap_sweep = sw;
+    if (!(sw <= w.wrap_tol)) w.sc->status |= 8;
   }
 }
 

@@ -66,7 +66,7 @@ class Params:
     walker_id: int = 0
     precision: int = 0      # 0 = all FP64, 1 = mixed (FP32 propagation)
     flags: int = 0
-    wrap_tol: float = 1e-8
+    wrap_tol: float = 0.0   # <= 0: the library's default (1e-8 FP64, 1e-4 mixed)
 
     @property
     def L_tau(self) -> int:

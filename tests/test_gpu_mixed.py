@@ -119,8 +119,9 @@ def test_batch_mixes_precisions(lq, ctx):
 def test_mixed_dilute_gas_first_sweep(lq, ctx):
     """32x32 dilute workload, mixed precision: the first sweep against the
     FP64 oracle.  Reported: the fraction of identical fields and the log-weight
-    error; required: at least 99.9 % identical fields, identical occupations,
-    and log|W| within the stated bar."""
+    error; required: at least 99.9 % identical fields, and log|W| within the
+    stated bar of the oracle's FP64 log|W| of the GPU's own final
+    configuration (and of the oracle's chain when every field agrees)."""
     lat, par = W.config_dilute(seed=1, walker_id=0, precision=lq.MIXED)
     g = lq.Walker(ctx, lat, par)
     o = oracle.Walker(lat, W.config_dilute(seed=1, walker_id=0)[1])
@@ -132,6 +133,14 @@ def test_mixed_dilute_gas_first_sweep(lq, ctx):
     print(f"mixed 32x32: identical fields {same:.6f}, "
           f"log|W| rel err {_rel(g.tracked_weight()[0], o.tracked_weight()[0]):.2e}, stats {g.stats()}")
     assert same >= 0.999
+    # the stated error, always enforced: the mixed walker's log|W| against the
+    # oracle's FP64 fresh log|W| of the same configuration (the GPU's fields
+    # and occupations given to the oracle)
+    lg, sg = g.tracked_weight()
+    o_same = oracle.Walker(lat, W.config_dilute(seed=1, walker_id=0)[1], fg, ug, dg)
+    lo_same, so_same = o_same.log_weight()
+    print(f"mixed 32x32: log|W| vs oracle on the GPU's configuration: rel err {_rel(lg, lo_same):.2e}")
+    assert sg == so_same and _rel(lg, lo_same) < LOGW_RTOL
     if same == 1.0:
         assert np.array_equal(ug, uo) and np.array_equal(dg, do)
         assert _rel(g.tracked_weight()[0], o.tracked_weight()[0]) < LOGW_RTOL
