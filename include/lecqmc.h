@@ -62,6 +62,7 @@ extern "C" {
 #define LECQMC_NO_FLIPS 2     /* flags: skip the Ising flips (fields frozen)          */
 
 #define LECQMC_MAX_NE 256     /* largest particle number per spin handled on device  */
+#define LECQMC_STATIC_MAX_WALKERS 1024 /* walkers per lecqmc_sweep_batch_static call  */
 
 /* Flags not provided: a symmetric checkerboard split (e^{-dtau K/2} on both
  * sides of D_l) and heat-bath acceptance.  The paper fixes neither; the
@@ -157,6 +158,15 @@ int lecqmc_sweep(lecqmc_walker *w, int32_t n_sweeps, int32_t do_measure);
  * distinct walkers (LECQMC_EINVAL if one appears twice).  The descriptor
  * array is grown with hipMalloc when n exceeds every earlier call's. */
 int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure);
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): lecqmc_sweep_batch with the walker descriptors
+ * staged in a fixed per-device array of LECQMC_STATIC_MAX_WALKERS entries
+ * (528 KiB, held until the process ends) instead of a grown allocation.  It
+ * calls no hipMalloc, hipFree or other allocating routine and records no
+ * phase timing.  n > LECQMC_STATIC_MAX_WALKERS: LECQMC_EINVAL.  All calls on
+ * one GPU share that array: calls that overlap on one GPU (from contexts on
+ * different streams) race, so callers serialise them. */
+int lecqmc_sweep_batch_static(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps, int32_t do_measure);
 
 /* A fixed batch of walkers of one context (uneven shapes and precisions
  * allowed): their descriptors are uploaded once, so lecqmc_batch_sweep only

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -31,8 +32,19 @@ static int fail(int code, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(LECQMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Descriptor staging of lecqmc_sweep_batch_static: one array in each
+// device's memory, held until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (lecqmc_ctx_create), and is kept in
+// g_scratch_addr.
+constexpr int kStaticMaxWalkers = LECQMC_STATIC_MAX_WALKERS;
+static __device__ __align__(256) unsigned char scratch[kStaticMaxWalkers * sizeof(WalkerDesc)];
+static std::mutex g_scratch_mu;
+static std::map<int, WalkerDesc *> g_scratch_addr;
+
 struct lecqmc_ctx {
   int device;
+  WalkerDesc *scratch_desc;   // this device's copy of scratch (device address)
   hipStream_t stream;
   bool own_stream;
   size_t budget, used;
@@ -355,8 +367,22 @@ extern "C" int lecqmc_ctx_create(int device, void *stream, size_t budget, lecqmc
   HIPCHK(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(LECQMC_EINVAL, "device %d not present (%d devices)", device, ndev);
   HIPCHK(hipSetDevice(device));
+  WalkerDesc *sd = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it == g_scratch_addr.end()) {
+      void *p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(LECQMC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      it = g_scratch_addr.emplace(device, (WalkerDesc *)p).first;
+    }
+    sd = it->second;
+  }
   lecqmc_ctx *c = new lecqmc_ctx();
   c->device = device;
+  c->scratch_desc = sd;
   c->budget = budget;
   c->used = 0;
   c->d_batch = nullptr;
@@ -757,6 +783,21 @@ extern "C" int lecqmc_sweep_batch(lecqmc_walker *const *ws, int32_t n, int32_t n
     c->batch_cap = cap;
   }
   return batch_run(c, order, n64, c->d_batch, n_sweeps, do_measure, true);
+}
+
+// The same sweeps with the descriptors staged in the device's static array
+// (no allocation of any kind; phase timing is not recorded).
+extern "C" int lecqmc_sweep_batch_static(lecqmc_walker *const *ws, int32_t n, int32_t n_sweeps,
+                                         int32_t do_measure) {
+  if (n > kStaticMaxWalkers)
+    return fail(LECQMC_EINVAL, "sweep_batch_static: %d walkers, at most %d", n, kStaticMaxWalkers);
+  std::vector<lecqmc_walker *> order;
+  order.reserve(n > 0 ? n : 0);
+  int n64 = 0;
+  if (int rc = batch_order(ws, n, n_sweeps, order, &n64)) return rc;
+  lecqmc_ctx *c = order[0]->ctx;
+  HIPCHK(hipSetDevice(c->device));
+  return batch_run(c, order, n64, c->scratch_desc, n_sweeps, do_measure, false);
 }
 
 // ---------------------------------------------------------------------------

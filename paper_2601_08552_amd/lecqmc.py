@@ -33,7 +33,9 @@ EXPORTED = [
     "lecqmc_set_state", "lecqmc_green", "lecqmc_flip_ratio", "lecqmc_swap_ratio", "lecqmc_last_error",
     "lecqmc_batch_create", "lecqmc_batch_sweep", "lecqmc_batch_destroy",
     "lecqmc_get_shape", "lecqmc_set_shape", "lecqmc_autotune", "lecqmc_ctx_query",
+    "lecqmc_sweep_batch_static",
 ]
+STATIC_MAX_WALKERS = 1024
 
 
 class LecqmcError(RuntimeError):
@@ -110,6 +112,7 @@ def load():
             "lecqmc_destroy_walker": (C.c_int, [vp]),
             "lecqmc_sweep": (C.c_int, [vp, i32, i32]),
             "lecqmc_sweep_batch": (C.c_int, [C.POINTER(vp), i32, i32, i32]),
+            "lecqmc_sweep_batch_static": (C.c_int, [C.POINTER(vp), i32, i32, i32]),
             "lecqmc_log_weight": (C.c_int, [vp, C.POINTER(dbl), C.POINTER(i32)]),
             "lecqmc_tracked_weight": (C.c_int, [vp, C.POINTER(dbl), C.POINTER(i32)]),
             "lecqmc_obs_size": (i64, [vp]),
@@ -340,6 +343,13 @@ def autotune(walkers):
 def sweep_batch(walkers, n_sweeps=1, measure=False):
     arr = (C.c_void_p * len(walkers))(*[w.h for w in walkers])
     _check(load().lecqmc_sweep_batch(arr, len(walkers), n_sweeps, 1 if measure else 0))
+
+
+def sweep_batch_static(walkers, n_sweeps=1, measure=False):
+    """sweep_batch through the entry point that allocates no device memory
+    (descriptors staged in the library's fixed per-device array)."""
+    arr = (C.c_void_p * len(walkers))(*[w.h for w in walkers])
+    _check(load().lecqmc_sweep_batch_static(arr, len(walkers), n_sweeps, 1 if measure else 0))
 
 
 class Batch:
