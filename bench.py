@@ -1,23 +1,35 @@
 """Throughput of the canonical-ensemble DQMC hot path on one MI355X.
 
-Workload: the dilute Fermi gas, 32x32 periodic Hubbard lattice (N = 1024),
-t = 1, U = 4, 8 up + 8 down particles, beta = 16, dtau = 0.05 (320 slices),
-QR every 10 slices, all FP64, 64 independent walkers (seeds 1..64) advanced
-together (one workgroup per walker).  A step is one full sweep of every
+Headline workload (value): the batched uneven walkers, 256 independent
+chains in one fixed batch, L x L periodic square lattices with L uniform in
+{16, 24, 32, 48, 64} (N = 256..4096), Ne per spin uniform in [4, 32], U
+uniform in [2, 6], beta in {8, 16}, dtau = 0.05, a QR every 10 slices, FP64,
+chain shapes autotuned, every sweep one HIP graph replay.  It is the largest
+fixed configuration that runs on one GPU.  A step is one full sweep of every
 walker: left-stack build, forward pass with N * L_tau Ising-flip attempts and
 QR stabilisation, and N_sigma particle-hole swaps per spin.
 
-Prints one JSON line.  value = HS-field updates per second (flip attempts of
-all walkers / wall time of the timed sweeps, inputs already resident) of the
-all-FP64 path; the "mixed" object gives the same measurement with the slice
-propagation in FP32 (QR, inverses, ratios and weights FP64) and its error.
+Also measured, as objects of the same JSON line:
+- dilute_gas: the 32x32 dilute Fermi gas (N = 1024, 8 + 8, beta = 16,
+  320 slices), 64 walkers, FP64 and mixed precision (FP32 propagation);
+- flat_band: the 256-cell flat-band chain (N = 512, 128 + 128, beta = 10),
+  128 walkers;
+- serving: a Poisson stream of simulation requests (50/s, L x L from 16 to
+  128, Ne per spin 4..64, U 2..8, beta 4..32, 100..1000 sweeps each)
+  admitted by device footprint over a fixed window;
+- accuracy: one walker of each workload swept on the GPU and by the FP64
+  oracle from the same state, in this run;
+- cpu_baseline: the FP64 oracle on the host cores on a stratified sample of
+  the headline workload's walkers.
+
+Prints one JSON line; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import multiprocessing as mp
 import os
+import subprocess
 import sys
 import time
 
@@ -26,12 +38,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-N_WALKERS = 64
 HBM_PEAK_GBS = 8000.0
+METRIC = "HS-field updates/s per GPU at stated err vs FP64 oracle; p50/p99 sweep latency"
 
 
 def algorithmic_bytes_forward(N, ne_up, ne_dn, L, nstab):
-    """Algorithmic HBM bytes of one forward-pass launch for one walker (FP64).
+    """Algorithmic HBM bytes of one walker's forward pass (FP64).
 
     Per slice each spin streams Phi_R and Phi_L (N x Ne) in and out once
     (diagonal factor, flips and checkerboard applied while resident):
@@ -39,56 +51,11 @@ def algorithmic_bytes_forward(N, ne_up, ne_dn, L, nstab):
     reads Phi twice and writes Q twice and the fresh Phi_L is read once:
     5 * N * Ne * 8.  Fields: one read and one write byte per site and slice.
     """
-    per_spin_slice = lambda ne: 4 * N * ne * 8
-    per_spin_block = lambda ne: 5 * N * ne * 8
     nblk = (L + nstab - 1) // nstab
     b = 0
     for ne in (ne_up, ne_dn):
-        b += L * per_spin_slice(ne) + nblk * per_spin_block(ne)
-    b += 2 * L * N
-    return b
-
-
-def measured_traffic(kernel_src, pmc_json):
-    """HBM bytes per k_forward launch from the committed rocprofv3 counters,
-    or None when the kernel source changed since they were taken."""
-    import hashlib
-    try:
-        rec = json.load(open(pmc_json))
-        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    except (OSError, ValueError):
-        return None
-    if rec.get("src_sha256") != sha:
-        return None
-    kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + rec["write_kib_per_dispatch"] * rec["write_scale"]
-    return kib * 1024.0
-
-
-def _oracle_worker(args):
-    seed, sweeps = args
-    import oracle
-    from paper_2601_08552_amd import workloads as W
-    lat, par = W.config_dilute(seed=seed, walker_id=seed - 1)
-    w = oracle.Walker(lat, par)
-    t0 = time.perf_counter()
-    w.sweep(sweeps)
-    return time.perf_counter() - t0
-
-
-def cpu_baseline(procs, sweeps):
-    """The FP64 oracle, unmodified, one walker per process on the host cores."""
-    from paper_2601_08552_amd import workloads as W
-    lat, par = W.config_dilute()
-    ctxm = mp.get_context("spawn")
-    t0 = time.perf_counter()
-    with ctxm.Pool(procs) as pool:
-        times = pool.map(_oracle_worker, [(s + 1, sweeps) for s in range(procs)])
-    wall = time.perf_counter() - t0
-    upd = procs * sweeps * lat.n_sites * par.L_tau
-    return {"value": upd / max(times), "unit": "HS-field updates/s", "cores": procs, "kind": "oracle",
-            "sample": f"{procs} walkers x {sweeps} sweep(s) of the 32x32 dilute workload, one process per core "
-                      f"(rate = updates / slowest process time; pool wall {wall:.1f} s)",
-            "sec_per_sweep_per_core": float(np.median(times) / sweeps)}
+        b += L * 4 * N * ne * 8 + nblk * 5 * N * ne * 8
+    return b + 2 * L * N
 
 
 def note(msg):
@@ -96,23 +63,99 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def pct(v):
+    return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99))} if len(v) else None
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, one plain process per host core (no process pool,
+# so nothing outlives the benchmark)
+# ---------------------------------------------------------------------------
+def oracle_child(spec_json):
+    """Run one walker of the oracle and print its per-sweep seconds (child process)."""
+    import oracle
+    from paper_2601_08552_amd import workloads as W
+    spec = json.loads(spec_json)
+    lat = W.square_lattice(spec["L"])
+    par = W.Params(**spec["par"])
+    w = oracle.Walker(lat, par)
+    times = []
+    for _ in range(spec["sweeps"]):
+        t0 = time.perf_counter()
+        w.sweep(1)
+        times.append(time.perf_counter() - t0)
+    print(json.dumps({"times": times, "updates": lat.n_sites * par.L_tau}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, procs):
+    """The FP64 oracle, unmodified, on `procs` host cores: a stratified sample
+    of `procs` walkers of the batched workload (sorted by N * L_tau * Ne^2,
+    every 256/procs-th), one sweep each, one process per walker.  The rate is
+    scaled to the whole workload: the sampled walkers' seconds per update,
+    weighted by the updates of the walkers each one stands for, spread over
+    the cores."""
+    import oracle
+    oracle.build()
+    order = sorted(range(len(cfg)), key=lambda c: cfg[c][0].n_sites * cfg[c][1].L_tau * cfg[c][1].n_up ** 2)
+    stride = max(1, len(cfg) // procs)
+    picks = [order[min(len(order) - 1, k * stride + stride // 2)] for k in range(procs)]
+    kids = []
+    for c in picks:
+        lat, par = cfg[c]
+        L = int(round(np.sqrt(lat.n_sites)))
+        spec = {"L": L, "sweeps": 1, "par": {k: getattr(par, k) for k in ("U", "beta", "dtau", "n_stab", "n_up",
+                                                                          "n_dn", "seed", "walker_id")}}
+        kids.append(subprocess.Popen([sys.executable, "-c", "import bench; bench.oracle_child(%r)" % json.dumps(spec)],
+                                     cwd=ROOT, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                                     env={**os.environ, "OMP_NUM_THREADS": "1"}))
+    t0 = time.perf_counter()
+    res = []
+    for k in kids:
+        out, _ = k.communicate()
+        res.append(json.loads(out.decode().strip().splitlines()[-1]))
+    wall = time.perf_counter() - t0
+    # seconds per update of each sample, standing for its stratum of walkers
+    spu = [r["times"][0] / r["updates"] for r in res]
+    strata = [order[k * stride:(k + 1) * stride] if k < procs - 1 else order[k * stride:] for k in range(procs)]
+    upd_total = sum(cfg[c][0].n_sites * cfg[c][1].L_tau for c in range(len(cfg)))
+    est_seconds = sum(spu[k] * sum(cfg[c][0].n_sites * cfg[c][1].L_tau for c in strata[k]) for k in range(procs))
+    per_sweep = [r["times"][0] for r in res]
+    return {"value": upd_total / (est_seconds / procs), "unit": "HS-field updates/s", "cores": procs,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{procs} of the 256 batched walkers (stratified by N*L_tau*Ne^2), one sweep each, one "
+                      f"process per core, {wall:.1f} s wall; rate = the whole batch's updates over its estimated "
+                      f"oracle time on {procs} cores (per-update cost of each sample times the updates of its "
+                      f"stratum)",
+            "sec_per_sweep_sampled": pct(per_sweep),
+            "us_per_update_sampled": {"min": 1e6 * min(spu), "max": 1e6 * max(spu)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--walkers", type=int, default=N_WALKERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dilute", action="store_true", help="skip the 32x32 dilute-gas objects")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default flip-chain shapes")
-    ap.add_argument("--no-uneven", action="store_true", help="skip the 256-walker uneven batch")
     ap.add_argument("--no-flat", action="store_true", help="skip the 128-walker flat-band batch")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--serve-window", type=float, default=60.0, help="seconds of the serving stream")
     ap.add_argument("--cpu-procs", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -120,145 +163,60 @@ def main():
     from paper_2601_08552_amd import workloads as W
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    ctx = lecqmc.Context(0, stream=stream)
 
-    def run(precision):
-        """Timed batched sweeps of the workload at one precision."""
-        note(f"dilute workload, precision {precision}: creating {args.walkers} walkers")
-        walkers = []
-        for s in range(args.walkers):
-            lat, par = W.config_dilute(seed=s + 1, walker_id=s, precision=precision)
-            walkers.append(lecqmc.Walker(ctx, lat, par))
-        note("autotuning")
-        t_tune = time.perf_counter()
-        tuned = lecqmc.autotune(walkers) if not args.no_autotune else None
-        t_tune = time.perf_counter() - t_tune
-        for _ in range(args.warmup):
-            lecqmc.sweep_batch(walkers, 1)
-        ctx.synchronize()
-        note("timing")
-        ctx.set_timing(True)
-        ctx.phase_times()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev[0].record(stream)
-        for k in range(args.steps):
-            lecqmc.sweep_batch(walkers, 1)
-            ev[k + 1].record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms_phase, cnt = ctx.phase_times()
-        ctx.set_timing(False)
-        step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
-        # weight carried by the chain vs the FP64 fresh recomputation, walker 0
-        lt, _ = walkers[0].tracked_weight()
-        lf, _ = walkers[0].log_weight()
-        res = dict(wall=wall, ms_phase=ms_phase, cnt=cnt, step_ms=step_ms, stats=walkers[0].stats(),
-                   logw_rel_err=abs(lt - lf) / max(1.0, abs(lf)), lat=lat, par=par,
-                   shape={"tile": walkers[0].shape[0], "chunk": walkers[0].shape[1],
-                          "autotuned": tuned is not None, "tune_s": t_tune if tuned is not None else 0.0})
-        for w in walkers:
-            w.close()
-        return res
-
-    def run_uneven():
-        """The batched uneven-walker workload: 256 chains of mixed lattice size,
-        Ne and beta, autotuned, one fixed batch, each sweep a HIP graph replay."""
-        note("uneven batch: creating 256 walkers")
-        cfg = W.config_batched(256)
-        gs = torch.cuda.Stream()
-        gctx = lecqmc.Context(0, stream=gs)
-        ws = [lecqmc.Walker(gctx, lat, par) for lat, par in cfg]
-        note("uneven batch: autotuning")
-        t_tune = time.perf_counter()
-        res = lecqmc.autotune(ws)
-        t_tune = time.perf_counter() - t_tune
-        note("uneven batch: timing")
-        batch = lecqmc.Batch(ws)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=gs):
-            batch.sweep(1)
-        torch.cuda.synchronize()
-        graph.replay()                                 # warm-up sweep
-        torch.cuda.synchronize()
-        k = max(1, min(args.steps, 3))
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
-        t0 = time.perf_counter()
-        with torch.cuda.stream(gs):
-            ev[0].record(gs)
-            for q in range(k):
-                graph.replay()
-                ev[q + 1].record(gs)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        step_ms = [ev[q].elapsed_time(ev[q + 1]) for q in range(k)]
-        upd = sum(lat.n_sites * par.L_tau for lat, par in cfg) * k
-        fwd = sorted(r[2] for r in res)
-        out = {"value": upd / wall, "unit": "HS-field updates/s", "walkers": len(ws), "steps": k,
-               "ms_per_step": wall * 1e3 / k,
-               "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
-               "updates_per_sweep": upd // k, "hbm_gib": gctx.bytes_in_use() / 2**30,
-               "autotune_s": t_tune, "shapes": {f"{t},{c}": sum(1 for r in res if r[:2] == (t, c))
-                                                 for (t, c) in sorted({r[:2] for r in res})},
-               "forward_ms_per_walker": {"min": fwd[0], "median": fwd[len(fwd) // 2], "max": fwd[-1]},
-               "config": "256 chains: L x L square, L in {16,24,32,48,64}, Ne per spin in [4,32], U in [2,6], "
-                         "beta in {8,16}, dtau=0.05, QR every 10 slices, FP64; sweeps replayed from a HIP graph"}
-        batch.close()
-        gctx.close()
-        return out
-
-    def run_flat():
-        """The flat-band workload: 128 walkers of the 256-cell chain (512
-        sites), flat band half filled with no imbalance (128 + 128), beta = 10,
-        autotuned, one batched sweep timed after a warm-up sweep."""
-        lat, par = W.config_flat_band(256, imbalance=0, beta=10.0)
-        fctx = lecqmc.Context(0, stream=stream)
-        mk = lambda s: lecqmc.Walker(fctx, lat, W.Params(**{**par.__dict__, "seed": s + 1, "walker_id": s}))
-        # every walker has the same shape key: tune on eight, the context
-        # hands the choice to the walkers created after
-        note("flat band: autotuning on 8 walkers")
-        ws = [mk(s) for s in range(8)]
-        t_tune = time.perf_counter()
-        res = lecqmc.autotune(ws)
-        t_tune = time.perf_counter() - t_tune
-        note(f"flat band: creating 120 more walkers (shape {res[0][:2]})")
-        ws += [mk(s) for s in range(8, 128)]
-        note("flat band: warm-up sweep")
-        lecqmc.sweep_batch(ws, 1)
-        fctx.synchronize()
-        note("flat band: timed sweep")
-        t0 = time.perf_counter()
-        lecqmc.sweep_batch(ws, 1)
-        fctx.synchronize()
-        wall = time.perf_counter() - t0
-        upd = len(ws) * lat.n_sites * par.L_tau
-        out = {"value": upd / wall, "unit": "HS-field updates/s", "walkers": len(ws), "steps": 1,
-               "ms_per_step": wall * 1e3, "hbm_gib": fctx.bytes_in_use() / 2**30, "autotune_s": t_tune,
-               "chain_shape": {"tile": ws[-1].shape[0], "chunk": ws[-1].shape[1]},
-               "config": "flat-band chain, 256 cells (N=512), t=t'=1, U=2, 128+128 particles, beta=10, "
-                         "dtau=0.05 (200 slices), QR every 10 slices, FP64"}
-        for w in ws:
-            w.close()
-        fctx.close()
-        return out
-
-    r64 = run(lecqmc.FP64)
-    rmx = None if args.no_mixed else run(lecqmc.MIXED)
-    lat, par = r64["lat"], r64["par"]
-    N, L = lat.n_sites, par.L_tau
-    wall, ms_phase, cnt, step_ms = r64["wall"], r64["ms_phase"], r64["cnt"], r64["step_ms"]
-    updates = args.walkers * N * L * args.steps
-    value = updates / wall
+    # ------------------------------------------------------------------
+    # headline: the 256-walker uneven batch
+    # ------------------------------------------------------------------
+    note("uneven batch: creating 256 walkers")
+    cfg = W.config_batched(256)
+    gs = torch.cuda.Stream()
+    gctx = lecqmc.Context(0, stream=gs)
+    ws = [lecqmc.Walker(gctx, lat, par) for lat, par in cfg]
+    note("uneven batch: autotuning")
+    t_tune = time.perf_counter()
+    tuned = lecqmc.autotune(ws)
+    t_tune = time.perf_counter() - t_tune
+    # the forward-pass launch timed alone by the context's phase events (on
+    # the stream the kernels run on), then the batch captured into a graph
+    note("uneven batch: phase timing")
+    lecqmc.sweep_batch(ws, 1)
+    gctx.synchronize()
+    gctx.set_timing(True)
+    gctx.phase_times()
+    lecqmc.sweep_batch(ws, 2)
+    ms_phase, cnt = gctx.phase_times()
+    gctx.set_timing(False)
+    batch = lecqmc.Batch(ws)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        batch.sweep(1)
+    torch.cuda.synchronize()
+    note(f"uneven batch: {args.warmup} warm-up + {args.steps} timed graph replays")
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(gs):
+        ev[0].record(gs)
+        for q in range(args.steps):
+            graph.replay()
+            ev[q + 1].record(gs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[q].elapsed_time(ev[q + 1]) for q in range(args.steps)]
+    upd_sweep = sum(lat.n_sites * par.L_tau for lat, par in cfg)
+    value = upd_sweep * args.steps / wall
     fwd_ms = ms_phase[1] / max(cnt[1], 1)
-    alg = algorithmic_bytes_forward(N, par.n_up, par.n_dn, L, par.n_stab) * args.walkers
+    alg = sum(algorithmic_bytes_forward(lat.n_sites, par.n_up, par.n_dn, par.L_tau, par.n_stab) for lat, par in cfg)
     achieved = alg / (fwd_ms * 1e-3) / 1e9
-    st = r64["stats"]
-    traffic = measured_traffic(os.path.join(ROOT, "paper_2601_08552_amd", "csrc", "lecqmc_kernels.hip"),
-                               os.path.join(ROOT, "profiles", "k_forward_dilute32x32_64w_pmc.json"))
+    fwd_w = sorted(r[2] for r in tuned)
+    st0 = ws[0].stats()
+    hbm_gib = gctx.bytes_in_use() / 2**30
+    batch.close()
     out = {
-        "metric": "HS-field updates/s per GPU at stated err vs FP64 oracle; p50/p99 sweep latency",
+        "metric": METRIC,
         "value": value,
         "unit": "HS-field updates/s",
         "n_gpus": 1,
@@ -270,48 +228,136 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "dilute Fermi gas 32x32 Hubbard, U=4, 8+8 particles, beta=16, dtau=0.05, "
-                               "QR every 10 slices, FP64", "walkers": args.walkers, "N": N, "L_tau": L,
-                   "ne_per_spin": par.n_up},
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                       "note": "per-walker sweep latency = batched step time (all walkers advance together)"},
-        "chain_shape": r64["shape"],
+        "config": {"workload": "batched uneven walkers: 256 chains, L x L periodic square, L in {16,24,32,48,64}, "
+                               "Ne per spin in [4,32], U in [2,6], beta in {8,16}, dtau=0.05, QR every 10 slices, "
+                               "FP64, autotuned chain shapes, sweeps replayed from a HIP graph",
+                   "walkers": len(ws), "updates_per_sweep": upd_sweep, "hbm_gib": hbm_gib},
+        "latency_ms": {**pct(step_ms), "note": "per-walker sweep latency = batched step time (every walker "
+                                                "advances one sweep per step)"},
         "phase_ms_per_launch": {"left_stack": ms_phase[0] / max(cnt[0], 1), "forward": fwd_ms,
                                 "fock": ms_phase[2] / max(cnt[2], 1)},
-        "accuracy": {"vs_oracle": "bit-identical Markov chain; log-weight, Green's function and ratios "
-                                  "within 1e-10 relative (parity tests)",
-                     "logw_drift": st["logw_drift"], "max_wrap_err": st["max_wrap_err"],
-                     "logw_rel_err_vs_fresh_fp64": r64["logw_rel_err"]},
+        "autotune": {"seconds": t_tune,
+                     "shapes": {f"{t},{c}": sum(1 for r in tuned if r[:2] == (t, c))
+                                for (t, c) in sorted({r[:2] for r in tuned})},
+                     "forward_ms_per_walker": {"min": fwd_w[0], "median": fwd_w[len(fwd_w) // 2], "max": fwd_w[-1]}},
         "roofline": {"bound": "hbm", "kernel": "k_forward", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg,
-                     "note": "bound in practice by the dependent flip chain: %.1f ns per site per walker"
-                             % (fwd_ms * 1e6 / (N * L))},
+                     "note": "one launch = the forward pass of all 256 walkers; it lasts as long as its slowest "
+                             "walker (the dependent flip chain), not as long as its bytes take"},
+        "stats_walker0": {k: st0[k] for k in ("logw_drift", "max_wrap_err", "qr_shifted")},
     }
-    if rmx is not None:
-        mp_ = rmx["ms_phase"]
-        mc_ = rmx["cnt"]
-        out["mixed"] = {
-            "value": updates / rmx["wall"], "unit": "HS-field updates/s", "ms_per_step": rmx["wall"] * 1e3 / args.steps,
-            "dtype": "f32 propagation / f64 QR, inverses, ratios, weights",
-            "chain_shape": rmx["shape"],
-            "latency_ms": {"p50": float(np.percentile(rmx["step_ms"], 50)),
-                           "p99": float(np.percentile(rmx["step_ms"], 99))},
-            "phase_ms_per_launch": {"left_stack": mp_[0] / max(mc_[0], 1), "forward": mp_[1] / max(mc_[1], 1),
-                                    "fock": mp_[2] / max(mc_[2], 1)},
-            "accuracy": {"logw_rel_err_vs_fresh_fp64": rmx["logw_rel_err"],
-                         "logw_drift": rmx["stats"]["logw_drift"],
-                         "vs_oracle": "first sweep of the 32x32 workload: identical fields and log|W| within "
-                                      "1e-5 relative; estimators within 1e-4 (mixed parity tests)"},
-        }
-    if not args.no_uneven:
-        out["uneven_batch"] = run_uneven()
+    for w in ws:
+        w.close()
+    gctx.close()
+
+    ctx = lecqmc.Context(0, stream=torch.cuda.current_stream())
+    stream = torch.cuda.current_stream()
+
+    def run_dilute(precision, nw=64, steps=5, warmup=2):
+        """Timed batched sweeps of the 32x32 dilute gas at one precision."""
+        note(f"dilute gas, precision {precision}: {nw} walkers")
+        walkers = [lecqmc.Walker(ctx, *W.config_dilute(seed=s + 1, walker_id=s, precision=precision))
+                   for s in range(nw)]
+        tuned_d = lecqmc.autotune(walkers)
+        for _ in range(warmup):
+            lecqmc.sweep_batch(walkers, 1)
+        ctx.synchronize()
+        ctx.set_timing(True)
+        ctx.phase_times()
+        evd = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        evd[0].record(stream)
+        for k in range(steps):
+            lecqmc.sweep_batch(walkers, 1)
+            evd[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wl = time.perf_counter() - t1
+        msp, cn = ctx.phase_times()
+        ctx.set_timing(False)
+        smd = [evd[k].elapsed_time(evd[k + 1]) for k in range(steps)]
+        lat, par = W.config_dilute()
+        res = {"value": nw * lat.n_sites * par.L_tau * steps / wl, "unit": "HS-field updates/s",
+               "walkers": nw, "steps": steps, "ms_per_step": wl * 1e3 / steps, "latency_ms": pct(smd),
+               "phase_ms_per_launch": {"left_stack": msp[0] / max(cn[0], 1), "forward": msp[1] / max(cn[1], 1),
+                                       "fock": msp[2] / max(cn[2], 1)},
+               "chain_shape": {"tile": tuned_d[0][0], "chunk": tuned_d[0][1]}}
+        for w in walkers:
+            w.close()
+        return res
+
+    if not args.no_dilute:
+        out["dilute_gas"] = {"config": "32x32 periodic Hubbard, U=4, 8+8 particles, beta=16, dtau=0.05 "
+                                       "(320 slices), QR every 10 slices",
+                             "fp64": run_dilute(lecqmc.FP64)}
+        if not args.no_mixed:
+            out["dilute_gas"]["mixed"] = {**run_dilute(lecqmc.MIXED),
+                                          "dtype": "f32 propagation / f64 QR, inverses, ratios, weights"}
+
     if not args.no_flat:
-        out["flat_band"] = run_flat()
+        lat, par = W.config_flat_band(256, imbalance=0, beta=10.0)
+        fctx = lecqmc.Context(0, stream=stream)
+        mk = lambda s: lecqmc.Walker(fctx, lat, W.Params(**{**par.__dict__, "seed": s + 1, "walker_id": s}))
+        note("flat band: autotuning on 8 walkers")
+        fw = [mk(s) for s in range(8)]
+        tf = lecqmc.autotune(fw)
+        note(f"flat band: 120 more walkers (shape {tf[0][:2]})")
+        fw += [mk(s) for s in range(8, 128)]
+        lecqmc.sweep_batch(fw, 1)
+        fctx.synchronize()
+        fctx.set_timing(True)
+        fctx.phase_times()
+        t1 = time.perf_counter()
+        lecqmc.sweep_batch(fw, 1)
+        fctx.synchronize()
+        wl = time.perf_counter() - t1
+        msp, cn = fctx.phase_times()
+        fctx.set_timing(False)
+        out["flat_band"] = {"value": len(fw) * lat.n_sites * par.L_tau / wl, "unit": "HS-field updates/s",
+                            "walkers": len(fw), "steps": 1, "ms_per_step": wl * 1e3,
+                            "phase_ms_per_launch": {"left_stack": msp[0], "forward": msp[1], "fock": msp[2]},
+                            "hbm_gib": fctx.bytes_in_use() / 2**30,
+                            "chain_shape": {"tile": fw[-1].shape[0], "chunk": fw[-1].shape[1]},
+                            "config": "flat-band chain, 256 cells (N=512), t=t'=1, U=2, 128+128 particles, "
+                                      "beta=10, dtau=0.05 (200 slices), QR every 10 slices, FP64"}
+        for w in fw:
+            w.close()
+        fctx.close()
+
+    if not args.no_serving:
+        from paper_2601_08552_amd import serve
+        note(f"serving: {args.serve_window:.0f} s window of the 50/s request stream")
+        out["serving"] = serve.serving_window(args.serve_window, rate=50.0, seed=0,
+                                              budget_bytes=int(200 * 2**30), log=note)
+
+    if not args.no_accuracy:
+        import oracle
+        acc = {}
+        for name, (lat, par) in (("batched_walker0", cfg[min(range(len(cfg)), key=lambda c: cfg[c][0].n_sites
+                                                                              * cfg[c][1].L_tau)]),
+                                 ("dilute_gas", W.config_dilute(seed=1))):
+            note(f"accuracy: {name} vs the oracle, one sweep")
+            g = lecqmc.Walker(ctx, lat, par)
+            o = oracle.Walker(lat, par)
+            lf, lo = g.log_weight()[0], o.log_weight()[0]
+            g.sweep(1)
+            o.sweep(1)
+            sg, so = g.state(), o.state()
+            same = all(np.array_equal(np.asarray(a), np.asarray(b)) for a, b in zip(sg, so))
+            lt, lto = g.tracked_weight()[0], o.tracked_weight()[0]
+            acc[name] = {"N": lat.n_sites, "ne": [par.n_up, par.n_dn], "L_tau": par.L_tau,
+                         "fresh_logw_rel_err": abs(lf - lo) / max(1.0, abs(lo)),
+                         "chain_identical_after_sweep": bool(same),
+                         "tracked_logw_rel_err_after_sweep": abs(lt - lto) / max(1.0, abs(lto))}
+            g.close()
+        out["accuracy"] = acc
+    ctx.close()
+
     if not args.no_cpu_baseline:
-        note("cpu baseline (the oracle on the host cores)")
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(procs, args.cpu_sweeps)
+        note(f"cpu baseline: the oracle on {procs} host cores")
+        out["cpu_baseline"] = cpu_baseline(cfg, procs)
     print(json.dumps(out), flush=True)
 
 

@@ -183,8 +183,12 @@ int lecqmc_batch_destroy(lecqmc_batch *b);
 
 /* Flip-chain shape of a walker.  tile = register tile T in {1, 2, 4}: the
  * Ne x Ne inverse of each spin is held in registers of one wavefront, which
- * needs Ne <= 8T; tile = 0: the inverse stays in LDS (any Ne).  chunk = sites
- * staged per step of the chain: 4, 8, 16 or 32.  New walkers take a default
+ * needs Ne <= 8T; tile = 0: the inverse stays in LDS (any Ne); tile = 9:
+ * delayed (submatrix) updates of chunks of sites on the vector units (any
+ * Ne, chunk <= 16); tile = 10: delayed updates of 16-site chunks on the FP64
+ * matrix cores (Ne <= 128, chunk 16; the decisions by Gauss-Jordan sweeps of
+ * the chunk's 16 x 16 matrix, the inverse by the Woodbury identity).
+ * chunk = sites staged per step of the chain: 4, 8, 16 or 32.  New walkers take a default
  * by Ne, or the shape an earlier lecqmc_autotune chose in the same context
  * for the same (n_sites, n_up, n_dn, precision).  Every shape samples the
  * same chain: the tile changes only the rounding order of the ratio sums,

@@ -116,26 +116,39 @@ extern "C" const char *lecqmc_last_error(void) { return g_err; }
 // Defaults by Ne, from measurements of the forward pass; lecqmc_autotune
 // replaces them by timed choices.  Every shape samples the same chain; the
 // shape changes only the rounding of the ratios.
-static bool shape_valid(int mmax, int tile, int chunk);
-static void shape_default(int mmax, int *tile, int *chunk) {
-  *tile = mmax <= 8 ? 1 : mmax <= 16 ? 2 : mmax <= 32 ? 4 : kDelayed;
-  *chunk = mmax <= 16 ? 32 : mmax <= 32 ? 16 : 8;
-  if (*tile == kDelayed && !shape_valid(mmax, *tile, *chunk)) *chunk = 4;
+static bool shape_valid(int ne0, int ne1, int tile, int chunk);
+static void shape_default(int ne0, int ne1, int *tile, int *chunk) {
+  const int mmax = std::max(1, std::max(ne0, ne1));
+  *tile = mmax <= 8 ? 1 : mmax <= 16 ? 2 : mmax <= 32 ? 4 : mmax <= kMfmaMaxNe ? kMfma : kDelayed;
+  *chunk = mmax <= 16 ? 32 : mmax <= 32 ? 16 : *tile == kMfma ? kMS : 8;
+  if (*tile == kMfma && !shape_valid(ne0, ne1, *tile, *chunk)) {
+    *tile = kDelayed;
+    *chunk = 8;
+  }
+  if (*tile == kDelayed && !shape_valid(ne0, ne1, *tile, *chunk)) *chunk = 4;
 }
 // row stride of the staged chunk rows: 8T for a register tile; Ne, or the
 // next odd number for the delayed chain (its threads read rows side by side)
 static int shape_xld(int mmax, int tile) {
-  return tile == kDelayed ? (mmax | 1) : tile > 0 ? 8 * tile : mmax;
+  return (tile == kDelayed || tile == kMfma) ? (mmax | 1) : tile > 0 ? 8 * tile : mmax;
 }
-static bool shape_valid(int mmax, int tile, int chunk) {
-  if (!(tile == 0 || tile == 1 || tile == 2 || tile == 4 || tile == kDelayed)) return false;
-  if (tile > 0 && tile != kDelayed && mmax > 8 * tile) return false;
+// LDS doubles of a shape's chunk matrices (0 for the site-by-site chains)
+// (the matrix-core chain needs only G and Z in LDS: U, W move to device
+// memory when the launch has no room for them)
+static int shape_dgn(int ne0, int ne1, int tile, bool full = false) {
+  return tile == kDelayed ? 4 * kDS * kDS : tile == kMfma ? (full ? mfma_lds_doubles(ne0, ne1) : mfma_lds_small()) : 0;
+}
+static bool shape_valid(int ne0, int ne1, int tile, int chunk) {
+  const int mmax = std::max(1, std::max(ne0, ne1));
+  if (!(tile == 0 || tile == 1 || tile == 2 || tile == 4 || tile == kDelayed || tile == kMfma)) return false;
+  if (tile > 0 && tile != kDelayed && tile != kMfma && mmax > 8 * tile) return false;
   if (!(chunk == 4 || chunk == 8 || chunk == 16 || chunk == 32)) return false;
   if (tile == kDelayed && chunk > 16) return false;   // the delayed chain's registers hold 16 sites
+  if (tile == kMfma && (chunk != kMS || mmax > kMfmaMaxNe)) return false;   // one 16-wide tile per chunk
   // both staging buffers (streamed walker) must fit next to the fixed layout,
   // with the Ne x Ne work matrices moved to device memory if need be (the
   // launch planner does that when they do not fit)
-  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, 1, tile == kDelayed ? 4 * kDS * kDS : 0};
+  const LdsPlan p{mmax, 0, 1, 0, 4 * chunk * shape_xld(mmax, tile), chunk, 1, shape_dgn(ne0, ne1, tile)};
   return lds_bytes(p) <= kLdsLimit;
 }
 static void shape_apply(WalkerDesc &h, int tile, int chunk) {
@@ -183,7 +196,7 @@ static LdsPlan plan_for(LdsPlan p, const std::vector<long> &needs, int bond_need
 // Walkers of one launch share a precision (the sweep launchers group them).
 // Resident blocks are counted in doubles: FP32 storage needs half of them.
 static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
-  int mm = 1, bonds = 0, slots = 1, xs = 0, smax = 0, tile = n > 0 ? ws[0]->h.tile : 0, dgn = 0;
+  int mm = 1, bonds = 0, slots = 1, xs = 0, smax = 0, tile = n > 0 ? ws[0]->h.tile : 0, dgn = 0, dgn_min = 0;
   std::vector<long> fwd, left, fock, fresh;
   bool compact = true;
   const int mixed = n > 0 ? ws[0]->h.mixed : 0;
@@ -201,7 +214,8 @@ static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
     bonds = std::max(bonds, w->h.bond_words);
     slots = std::max(slots, w->nblk - 1);
     if (w->h.tile != tile) tile = -1;
-    if (w->h.tile == kDelayed) dgn = 4 * kDS * kDS;
+    dgn = std::max(dgn, shape_dgn(w->ne[0], w->ne[1], w->h.tile, true));
+    dgn_min = std::max(dgn_min, shape_dgn(w->ne[0], w->ne[1], w->h.tile, false));
   }
   if (!compact) bonds = 0;
   // The fixed part of the plan takes each region's largest size over the
@@ -216,13 +230,21 @@ static LaunchCfg launch_cfg(lecqmc_walker *const *ws, int n) {
     worst.gm = 2;
     return lds_bytes(worst) <= kLdsLimit ? 2 : 1;
   };
+  // the matrix-core chain's U and W stay in LDS only when the launch has
+  // room for them next to everything else (staged right rows included)
+  if (dgn > dgn_min && lds_bytes(LdsPlan{mm, 0, 1, 0, xs, smax, 1, dgn}) > kLdsLimit) dgn = dgn_min;
   const int gmf = place(LdsPlan{mm, 0, 1, 0, xs, smax, 0, dgn});
   const int gm = place(LdsPlan{mm, 0, 0, 0, 0, 0, 0, 0});
   if (gm) slots = 1;   // one estimator workgroup per walker: its work matrices are one per walker
-  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm, 0}, fbase{mm, 0, 0, 0, xs, smax, gmf, dgn};
+  // the Fock phase keeps at least its Hessenberg work matrix in LDS when the
+  // others have to go (its Givens chain reads a row of it per step)
+  int gmk = gm;
+  if (gm == 1 && lds_bytes(LdsPlan{mm, 0, 0, 0, 0, 0, 3, 0}) + sizeof(double) * std::max(64, mm) <= kLdsLimit) gmk = 3;
+  const LdsPlan base{mm, 0, 0, 0, 0, 0, gm, 0}, fbase{mm, 0, 0, 0, xs, smax, gmf, dgn},
+      kbase{mm, 0, 0, 0, 0, 0, gmk, 0};
   LdsPlan fw = fbase;
   fw.stage_ps = 1;
-  return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(base, fock, bonds, false),
+  return {plan_for(fbase, fwd, bonds, true), plan_for(base, left, bonds, false), plan_for(kbase, fock, bonds, false),
           base,                              plan_for(base, fresh, bonds, false), slots,
           mixed,                             tile,
           lds_bytes(fw) <= kLdsLimit};
@@ -530,9 +552,9 @@ extern "C" int lecqmc_create_walker(lecqmc_ctx *ctx, const lecqmc_lattice *lat, 
   d.ne[0] = ne[0]; d.ne[1] = ne[1]; d.mmax = w->mmax;
   {
     int tile, chunk;
-    shape_default(w->mmax, &tile, &chunk);
+    shape_default(ne[0], ne[1], &tile, &chunk);
     auto it = ctx->tuned.find(std::make_tuple(N, ne[0], ne[1], d.mixed));
-    if (it != ctx->tuned.end() && shape_valid(w->mmax, it->second.first, it->second.second)) {
+    if (it != ctx->tuned.end() && shape_valid(ne[0], ne[1], it->second.first, it->second.second)) {
       tile = it->second.first;
       chunk = it->second.second;
     }
@@ -903,7 +925,7 @@ static int set_shape(lecqmc_walker *w, int tile, int chunk) {
 
 extern "C" int lecqmc_set_shape(lecqmc_walker *w, int32_t tile, int32_t chunk) {
   if (!w) return fail(LECQMC_EINVAL, "null walker");
-  if (!shape_valid(w->mmax, tile, chunk))
+  if (!shape_valid(w->ne[0], w->ne[1], tile, chunk))
     return fail(LECQMC_EINVAL, "shape (tile %d, chunk %d) not valid for Ne = %d", tile, chunk, w->mmax);
   if (w->batches > 0) return fail(LECQMC_ESTATE, "walker belongs to %d batch(es)", w->batches);
   HIPCHK(hipSetDevice(w->ctx->device));
@@ -915,7 +937,7 @@ extern "C" int lecqmc_set_shape(lecqmc_walker *w, int32_t tile, int32_t chunk) {
 // walker's device state is rebuilt by the next sweep), timed per walker by
 // the kernel's own wall clock.  The state is restored afterwards, so tuning
 // leaves the Markov chains where they were.
-constexpr int kTiles = 5;
+constexpr int kTiles = 6;
 extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *tile_out, int32_t *chunk_out,
                                double *fwd_ms_out) {
   if (!ws || n <= 0) return fail(LECQMC_EINVAL, "bad arguments");
@@ -976,14 +998,14 @@ extern "C" int lecqmc_autotune(lecqmc_walker *const *ws, int32_t n, int32_t *til
     if (e == hipSuccess)
       e = hipMemcpyAsync(snap + off[t] + align256(nf), ws[t]->h.sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st);
   }
-  static const int tiles[kTiles] = {1, 2, 4, 0, kDelayed}, chunks[4] = {4, 8, 16, 32};
+  static const int tiles[kTiles] = {1, 2, 4, 0, kDelayed, kMfma}, chunks[4] = {4, 8, 16, 32};
   for (int ti = 0; ti < kTiles && e == hipSuccess; ++ti)
     for (int ci = 0; ci < 4 && e == hipSuccess; ++ci)
       for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
         std::vector<lecqmc_walker *> g;
         std::vector<int> idx;
         for (int t = 0; t < n; ++t)
-          if (ws[t]->h.mixed == pass && shape_valid(ws[t]->mmax, tiles[ti], chunks[ci])) {
+          if (ws[t]->h.mixed == pass && shape_valid(ws[t]->ne[0], ws[t]->ne[1], tiles[ti], chunks[ci])) {
             g.push_back(ws[t]);
             idx.push_back(t);
           }

@@ -11,6 +11,18 @@ constexpr int kMaxNe = 256;     // particles per spin
 constexpr int kLdsNe = 64;      // largest Ne whose Ne x Ne work matrices are kept in LDS
 constexpr int kDelayed = 9;     // chain shape code of the delayed (submatrix) flip update
 constexpr int kDS = 32;         // sites per chunk at most (accepted-site masks are 32 bits)
+constexpr int kMfma = 10;       // chain shape code of the delayed update on the FP64 matrix cores
+constexpr int kMS = 16;         // sites per chunk of that chain (one 16-wide matrix-core tile)
+// Ne rounded up to whole 16-row tiles
+__host__ __device__ inline int ne16(int ne) { return (ne + 15) & ~15; }
+constexpr int kMfmaMaxNe = 128; // largest Ne of that chain (its W tiles stay in registers)
+// LDS doubles of the matrix-core chain's chunk matrices for one walker: G
+// then Z (16 x 16, row stride 17) and two partial G (16 x 16) per spin, then
+// U (Ne x 16, row stride 17) per spin when it fits the launch
+__host__ __device__ inline int mfma_lds_small() { return 2 * 16 * 17 + 2 * 2 * 256; }
+__host__ __device__ inline int mfma_lds_doubles(int ne0, int ne1) {
+  return mfma_lds_small() + 17 * (ne16(ne0) + ne16(ne1));
+}
 
 // counter-based generator streams (shared layout with the walker's key)
 enum Stream : uint32_t { kFlip = 1, kSwapK = 2, kSwapJ = 3, kSwapAcc = 4, kInitField = 5, kInitOcc = 6 };
@@ -42,7 +54,8 @@ struct WalkerDesc {
   int ne[2];
   int mmax;                     // max(ne[0], ne[1], 1): stride of the per-level Fock scratch
   // shape of the flip chain (set by the host: default by Ne, or autotuned)
-  int tile;                     // register tile T (Ne <= 8T held in registers) or 0 (inverse in LDS)
+  int tile;                     // register tile T (Ne <= 8T held in registers), 0 (inverse in LDS),
+                                // kDelayed or kMfma (delayed chunk updates)
   int chunk;                    // sites per staged chunk, 4..32
   int xld;                      // row stride of the staged rows: 8T, or mmax when tile = 0
   uint64_t seed, wid;
@@ -106,7 +119,8 @@ struct LdsPlan {
   int mm, phi_elems, stage_ps, bond_words, xs_elems, smax;
   int gm;   // Ne x Ne work matrices: 0 all four in LDS, 2 the inverses in LDS and the scratch
             // pair in each walker's bigm, 1 all four in bigm
-  int dgn;  // LDS doubles for the delayed chain's chunk and coefficient matrices (4 kDS^2, or 0)
+  int dgn;  // LDS doubles for the delayed chains' chunk and coefficient matrices (4 kDS^2 for
+            // kDelayed, mfma_lds_doubles for kMfma, or 0)
 };
 // LDS doubles that a walker's resident blocks of `entries` elements need
 __host__ __device__ inline long phi_doubles(long entries, int elem_bytes) {

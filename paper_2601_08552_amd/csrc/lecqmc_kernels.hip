@@ -68,7 +68,8 @@ struct Lds {
   double *us;     // [2 buf][S]              staged uniforms
   double *dl;     // [2 buf][2 spin][S]      staged flip factors Delta
   int8_t *fs;     // [2 buf][S]              staged Ising fields
-  double *dg;     // delayed chain: [2 spin][kDS][kDS] chunk matrices, then as many coefficients, or nullptr
+  double *dg;     // delayed chains: chunk and coefficient matrices (dgn doubles), or nullptr
+  int dgn;
   double *phi;    // resident Slater blocks, or nullptr
   double *bonds;  // compact bond tables (coef | bij | bci), or nullptr
   int S;          // sites per staged chunk
@@ -80,7 +81,7 @@ struct Lds {
 __host__ __device__ inline int vec_len(int mm) { return mm > 64 ? mm : 64; }
 __host__ __device__ inline size_t lds_doubles_fixed(const LdsPlan &p) {
   const size_t mm = p.mm < 1 ? 1 : p.mm, S = p.smax > 0 ? p.smax : 0, vs = vec_len((int)mm);
-  const size_t mats = p.gm == 1 ? 0 : (p.gm == 2 ? 2 : 4) * mm * mm;
+  const size_t mats = (p.gm == 1 ? 0 : p.gm == 3 ? 1 : p.gm == 2 ? 2 : 4) * mm * mm;
   return 256 + 64 + mats + 8 * vs + 4 * vs + (p.stage_ps ? 2 : 1) * (size_t)p.xs_elems + 2 * S +
          4 * S + (2 * S + 7) / 8 + (size_t)p.dgn;
 }
@@ -105,9 +106,11 @@ __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   L.red = p; p += 256;
   L.scal = p; p += 64;
   L.Ms0 = L.Ms1 = L.A = L.B = nullptr;   // those not in LDS are bound per walker by bind_mats
-  if (LEAN || pl.gm != 1) {
+  if (LEAN || pl.gm == 0 || pl.gm == 2) {
     L.Ms0 = p; p += mm * mm;
     L.Ms1 = p; p += mm * mm;
+  } else if (pl.gm == 3) {
+    L.Ms0 = p; p += mm * mm;
   }
   if (LEAN || pl.gm == 0) {
     L.A = p; p += mm * mm;
@@ -123,8 +126,10 @@ __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   L.fs = reinterpret_cast<int8_t *>(p); p += (2 * S + 7) / 8;
   if (LEAN) {
     L.dg = nullptr;
+    L.dgn = 0;
   } else {
     L.dg = pl.dgn > 0 ? p : nullptr;
+    L.dgn = pl.dgn;
     p += pl.dgn;
   }
   L.phi = pl.phi_elems > 0 ? p : nullptr; p += pl.phi_elems;
@@ -136,17 +141,15 @@ __device__ __forceinline__ Lds carve(const LdsPlan &pl) {
   return L;
 }
 // Ne x Ne work matrices in device memory (plans with gm = 1: all four; gm =
-// 2: the scratch pair A, B): slot 0 for kernels with one workgroup per
-// walker, the spin for those with one per (walker, spin).  The matrices are
-// addressed with the walker's own Ne.
+// 2: the scratch pair A, B; gm = 3, the Fock phase only: all but the first):
+// slot 0 for kernels with one workgroup per walker, the spin for those with
+// one per (walker, spin).  The matrices are addressed with the walker's own Ne.
 __device__ __forceinline__ void bind_mats(Lds &L, const WalkerDesc &w, const LdsPlan &pl, int slot) {
   if (pl.gm == 0) return;
   const size_t q = (size_t)w.mmax * w.mmax;
   double *base = w.bigm + (size_t)slot * 4 * q;
-  if (pl.gm == 1) {
-    L.Ms0 = base;
-    L.Ms1 = base + q;
-  }
+  if (pl.gm == 1) L.Ms0 = base;
+  if (pl.gm == 1 || pl.gm == 3) L.Ms1 = base + q;
   L.A = base + 2 * q;
   L.B = base + 3 * q;
 }
@@ -1293,33 +1296,394 @@ __device__ __forceinline__ void delayed_epilogue(const WalkerDesc &w, Lds &L, do
   SYNC();
 }
 
+// ---------------------------------------------------------------------------
+// Delayed flip chain on the FP64 matrix cores (shape kMfma).  Per chunk of
+// 16 sites (one 16-wide tile) and per spin, with x_r the left rows, p_r the
+// right rows, M = M^{-1} and D = diag(Delta_r):
+//   U = M X (Ne x 16),  W = P M (16 x Ne),  G = P U (16 x 16)        [MFMA]
+// Wave 0 then decides the sites in order on G alone, by Gauss-Jordan sweeps
+// of A = I + G D (both spins, one in each half of the wave): the pivot of
+// site r is 1 + Delta_r G_t[r][r], the spin's ratio r_s with every earlier
+// accepted site of the chunk applied (a Schur complement), and an accepted
+// site is swept.  Once the accepted set S is swept, A[S,S] = -(I + G_SS D_S)^-1,
+// so the Woodbury identity gives the inverse of the flipped system,
+//   M <- M - U_S D_S (I + G_SS D_S)^{-1} W_S = M - U (Z W),
+//   Z = -D A[S,S] (zero outside S),                                   [MFMA]
+// the product of the chunk's Sherman-Morrison updates (main text, delay and
+// submatrix updates of the auxiliary-field sweep).
+// Operand layouts of v_mfma_f64_16x16x4f64 (lane l, c = l % 16, g = l / 16):
+// A (16 x 4) holds A[c][g], B (4 x 16) holds B[g][c], and element j of the
+// 16 x 16 result holds D[4 j + g][c].
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// The chain's chunk matrices.  U (Ne16 x 17 per spin, for the update) in LDS
+// or, when the launch has no room, in the walker's device scratch; the two
+// partial G of each spin (16 x 16, in MFMA result order) and G then Z
+// (16 x 17) in LDS.  W and Y never leave the registers of the wave that owns
+// their column tile.
+struct MfBufs {
+  double *U[2];
+  double *GP[2];   // [2 partials][4 x 64]
+  double *GZ[2];
+};
+__device__ __forceinline__ MfBufs mfbufs(const WalkerDesc &w, double *dg, bool u_lds) {
+  MfBufs b;
+  b.GZ[0] = dg;
+  b.GZ[1] = dg + 16 * 17;
+  b.GP[0] = dg + 2 * 16 * 17;
+  b.GP[1] = b.GP[0] + 2 * 256;
+  double *base = u_lds ? b.GP[1] + 2 * 256 : w.dch;
+  b.U[0] = base;
+  b.U[1] = base + 17 * ne16(w.ne[0]);
+  return b;
+}
+// U addressed in LDS or device memory
+template <typename PU> __device__ __forceinline__ PU uwp(double *p);
+template <> __device__ __forceinline__ lds_f64 *uwp<lds_f64 *>(double *p) { return as_lds(p); }
+template <> __device__ __forceinline__ double *uwp<double *>(double *p) { return p; }
+
+// Tiles of a chunk: wave w works for spin w / 2; it owns the W (and Y, and
+// update) column tiles t with t % 2 == w % 2 and the U row tiles with
+// t % 2 != w % 2, so a spin's two waves share its work whatever its tile
+// count.  At most kMfTiles column tiles per wave (Ne <= 128).
+constexpr int kMfTiles = 4;
+
+// sum_k A[c][k] B[k][.] over k < m for one 16 x 16 result tile, four
+// operand groups of four k per round, the next round's loads issued before
+// this round's MFMAs; lda(k) and ldb(k) load this lane's operands.
+template <typename LA, typename LB>
+__device__ __forceinline__ v4d mf_dot(v4d acc, int m, LA &&lda, LB &&ldb) {
+  const int g = (TID & 63) >> 4;
+  double a[4], b[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + g;
+      a[u] = k < m ? lda(k) : 0.0;
+      b[u] = k < m ? ldb(k) : 0.0;
+    }
+  };
+  if (m > 0) load(0);
+  for (int k0 = 0; k0 < m; k0 += 16) {
+    double a0[4], b0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { a0[u] = a[u]; b0[u] = b[u]; }
+    if (k0 + 16 < m) load(k0 + 16);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + 4 * u < m) acc = mfma_f64(a0[u], b0[u], acc);
+  }
+  return acc;
+}
+
+// Phase A (all waves): W tiles into registers; U tiles to U (LDS or device
+// memory) and, from their registers, the spin's partial G = P U of this
+// wave.  PM: the inverses; PP: the right rows (LDS, resident or staged).
+template <typename PU, typename PM, typename PP>
+__device__ __forceinline__ void mf_front(const WalkerDesc &w, const MfBufs &B, PM M0, PM M1, const double *xsb,
+                                         int xld, PP P0, PP P1, int lp0, int lp1, int cnt, v4d (&Wr)[kMfTiles]) {
+  const int lane = TID & 63, wave = TID >> 6, c = lane & 15, g = lane >> 4;
+  const int sp = wave >> 1, par = wave & 1, m = w.ne[sp], T = ne16(m) >> 4;
+  const PM M = sp ? M1 : M0;
+  const PP P = sp ? P1 : P0;
+  const int lp = sp ? lp1 : lp0;
+  const bool cok = c < cnt;
+  const lds_f64 *X = as_lds(xsb) + sp * kMS * xld;
+  // W[r][16t + i] = sum_k P[r][k] M[k][16t + i]
+#pragma unroll
+  for (int s = 0; s < kMfTiles; ++s) {
+    const int t = 2 * s + par;
+    Wr[s] = (v4d){0.0, 0.0, 0.0, 0.0};
+    if (t < T) {
+      const int col = 16 * t + c;
+      const bool colok = col < m;
+      Wr[s] = mf_dot(Wr[s], m, [&](int k) { return cok ? (double)P[c * lp + k] : 0.0; },
+                     [&](int k) { return colok ? (double)M[k * m + col] : 0.0; });
+    }
+  }
+  // U[16t + i][r] = sum_k M[16t + i][k] X[r][k]; then G += P[:, tile t] U_t
+  // with U_t's registers as the B operand (element j holds row 4j + g)
+  v4d gp = {0.0, 0.0, 0.0, 0.0};
+  PU U = uwp<PU>(B.U[sp]);
+  for (int t = 1 - par; t < T; t += 2) {
+    const int row = 16 * t + c;
+    const bool rok = row < m;
+    const v4d ut = mf_dot((v4d){0.0, 0.0, 0.0, 0.0}, m, [&](int k) { return rok ? (double)M[row * m + k] : 0.0; },
+                          [&](int k) { return cok ? X[c * xld + k] : 0.0; });
+#pragma unroll
+    for (int j = 0; j < 4; ++j) U[(16 * t + 4 * j + g) * 17 + c] = ut[j];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 16 * t + 4 * u;
+      if (k < m) gp = mfma_f64((cok && k + g < m) ? (double)P[c * lp + k + g] : 0.0, ut[u], gp);
+    }
+  }
+  lds_f64 *G = as_lds(B.GP[sp]) + par * 256;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) G[j * 64 + lane] = gp[j];
+}
+
+// One site of the decision chain (R fixed at compile time: the DPP row
+// broadcast takes its source lane as an immediate).  Lane (s, h, j) =
+// 32 s + 16 h + j holds rows 8h..8h+7 of column j of spin s's A = I + G D.
+struct MfSweep {
+  double a[8];
+  unsigned mask;
+  double prod;   // accepted-ratio product of the chunk, renormalised as in acc_ratio
+  int expo;
+};
+// a[q] <- a[q] + b * (a[q] of lane R of this lane's 16-lane row) for the
+// eight rows, one 64-bit DPP instruction each (row broadcast); the s_nop
+// covers a write of a broadcast register by the instruction just before
+template <int R>
+__device__ __forceinline__ void fma_bcast8(double (&a)[8], double b) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %0, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %1, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %2, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %3, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %4, %4, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %5, %5, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %6, %6, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %7, %7, %8 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+      : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]), "+v"(a[7])
+      : "v"(b), "n"(R));
+}
+template <int R>
+__device__ __forceinline__ void mf_site(MfSweep &S, int sp, int h, int j, double uu, int cnt) {
+  constexpr int HR = R >> 3, QR = R & 7;
+  if (R < cnt) {
+    // pivots of both spins (uniform), the ratio and the uniform of site R
+    const double pu = lane_read(S.a[QR], 16 * HR + R), pd = lane_read(S.a[QR], 32 + 16 * HR + R);
+    const double ratio = pu * pd;
+    const double ur = lane_read(uu, R);
+    if (__builtin_amdgcn_readfirstlane((int)(ur < fabs(ratio)))) {
+      const double pinv = div_nr(1.0, sp ? pd : pu);
+      // row R of this lane's column (held by the half HR)
+      const unsigned lo = (unsigned)__double2loint(S.a[QR]), hi = (unsigned)__double2hiint(S.a[QR]);
+      const auto xl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+      const auto xh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+      const double rowv = __hiloint2double((int)xh[HR], (int)xl[HR]);
+      const bool isr = j == R;
+      // A[i][j] -= A[i][R] A[R][j] / p; column R itself: A[i][R] <- A[i][R] / p,
+      // i.e. A - A (1 - 1/p); A[i][R] comes from lane R of the 16-lane row
+      const double nt = isr ? pinv - 1.0 : -(rowv * pinv);
+      const double pr_new = isr ? -pinv : rowv * pinv;
+      fma_bcast8<R>(S.a, nt);
+      if (h == HR) S.a[QR] = pr_new;
+      S.mask |= 1u << R;
+      const double pr = S.prod * fabs(ratio);
+      S.expo += __builtin_amdgcn_frexp_exp(pr);
+      S.prod = __builtin_amdgcn_frexp_mant(pr);
+    }
+  }
+  if constexpr (R + 1 < kMS) mf_site<R + 1>(S, sp, h, j, uu, cnt);
+}
+
+// Phase B (wave 0): A = I + G D with G the sum of the spin's two partials,
+// Gauss-Jordan sweeps of the accepted sites, then Z = -D A[S,S] into GZ.
+// Returns the accepted-site mask.
+__device__ __forceinline__ unsigned mf_decide(const MfBufs &B, const double *usb_g, const double *dsb_g, int cnt,
+                                              int S, ChainAcc &acc) {
+  const int lane = TID & 63, sp = lane >> 5, h = (lane >> 4) & 1, j = lane & 15;
+  const lds_f64 *usb = as_lds(usb_g);
+  const lds_f64 *dsb = as_lds(dsb_g) + sp * S;
+  const lds_f64 *gp = as_lds(B.GP[sp]);
+  lds_f64 *gz = as_lds(B.GZ[sp]);
+  const double dj = j < cnt ? dsb[j] : 0.0;
+  MfSweep st;
+  double dr[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int row = 8 * h + q;
+    // G[row][j] sits in result element row / 4 of lane 16 (row % 4) + j
+    const int ix = (row >> 2) * 64 + (row & 3) * 16 + j;
+    st.a[q] = fma(gp[ix] + gp[256 + ix], dj, row == j ? 1.0 : 0.0);
+    dr[q] = row < cnt ? dsb[row] : 0.0;
+  }
+  const double uu = j < cnt ? usb[j] : 2.0;
+  st.mask = 0u;
+  st.prod = 1.0;
+  st.expo = 0;
+  // the chunk's sites run from registers: the caller's accumulator is
+  // folded in once, after the chunk
+  mf_site<0>(st, sp, h, j, uu, __builtin_amdgcn_readfirstlane(cnt));
+  const unsigned mask = st.mask;
+  acc_ratio(acc, st.prod);
+  acc.expo += st.expo;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int row = 8 * h + q;
+    gz[row * 17 + j] = ((mask >> row) & (mask >> j) & 1u) ? -dr[q] * st.a[q] : 0.0;
+  }
+  acc.nacc += __builtin_popcount(mask);
+  return mask;
+}
+
+// Phase C (all waves): for each owned column tile t, Y_t = Z W_t with W_t's
+// registers as the B operand, then M[ta, t] -= U[ta, :] Y_t for every row
+// tile ta with Y_t's registers as the B operand.
+template <typename PU, typename PM>
+__device__ __forceinline__ void mf_back(const WalkerDesc &w, const MfBufs &B, PM M0, PM M1,
+                                        const v4d (&Wr)[kMfTiles]) {
+  const int lane = TID & 63, wave = TID >> 6, c = lane & 15, g = lane >> 4;
+  const int sp = wave >> 1, par = wave & 1, m = w.ne[sp], T = ne16(m) >> 4;
+  PM M = sp ? M1 : M0;
+  const lds_f64 *Z = as_lds(B.GZ[sp]);
+  const PU U = uwp<PU>(B.U[sp]);
+  double za[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) za[u] = Z[c * 17 + 4 * u + g];
+#pragma unroll
+  for (int s = 0; s < kMfTiles; ++s) {
+    const int t = 2 * s + par;
+    if (t >= T) break;
+    v4d y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y = mfma_f64(za[u], Wr[s][u], y);
+    const int col = 16 * t + c;
+    // the next row tile's operands are loaded before this tile's MFMAs
+    v4d cn;
+    double an[4];
+    auto load = [&](int ta) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * ta + 4 * j + g;
+        cn[j] = (row < m && col < m) ? (double)M[row * m + col] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) an[u] = -(double)U[(16 * ta + c) * 17 + 4 * u + g];
+    };
+    load(0);
+    for (int ta = 0; ta < T; ++ta) {
+      v4d acc = cn;
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = an[u];
+      if (ta + 1 < T) load(ta + 1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = mfma_f64(a[u], y[u], acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * ta + 4 * j + g;
+        if (row < m && col < m) M[row * m + col] = acc[j];
+      }
+    }
+  }
+}
+
+// One chunk of the matrix-core chain from its staged rows to the updated
+// inverse.  Wave 0 decides while waves 1..3 flush the previous chunk and
+// stage the next (the caller's callback).  PU: U in LDS or device memory;
+// PM: the inverses in LDS or device memory.
+template <typename PU, typename PM, typename PP, typename FS>
+__device__ __forceinline__ void mf_chunk(const WalkerDesc &w, Lds &L, const MfBufs &B, PM M0, PM M1,
+                                         const double *xsb, int xld, PP P0, PP P1, int lp0, int lp1, int cnt,
+                                         int bufi, ChainAcc &acc, FS &&side) {
+  const int S = L.S;
+  v4d Wr[kMfTiles];
+  mf_front<PU>(w, B, M0, M1, xsb, xld, P0, P1, lp0, lp1, cnt, Wr);
+  SYNC();
+  if (TID < 64) {
+    const unsigned mask = mf_decide(B, L.us + bufi * S, L.dl + bufi * 2 * S, cnt, S, acc);
+    if (TID == 0) L.iscal[8 + bufi] = (int)mask;
+  } else {
+    side();
+  }
+  SYNC();
+  if (L.iscal[8 + bufi] != 0) {
+    mf_back<PU>(w, B, M0, M1, Wr);
+    SYNC();
+  }
+}
+
 // Stage chunk c (rows i0 .. i0+cnt-1) of slice l into buffer bufi: left rows
 // (Phi_L'^T = E_K^T Y_l, stored by the left-stack build), right rows when
-// streamed, fields and the flip uniforms.  Threads t0.. of the caller.
+// streamed, fields and the flip uniforms.  Threads t0.. of the caller.  The
+// rows of a chunk are contiguous in device memory; each thread issues eight
+// loads (typed as global, so that they are not ordered behind the LDS
+// stores) before it stores them into the staging buffer of row stride mm.
+typedef __attribute__((address_space(1))) const float gc_f32;
+typedef __attribute__((address_space(1))) const double gc_f64;
+__device__ __forceinline__ gc_f64 *as_global(const double *p) { return (gc_f64 *)p; }
+__device__ __forceinline__ gc_f32 *as_global(const float *p) { return (gc_f32 *)p; }
 template <typename F>
 __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, int i0, int bufi,
                             F *const phi[2], bool resident, int mm, int t0, int nt) {
   if (TID < t0 || TID >= t0 + nt) return;
   const int S = L.S, N = w.N;
   const int cnt = min(S, N - i0);
+  const int tid = TID - t0, tot = cnt * mm;
+  const int dr = nt / mm, da = nt - dr * mm;
+  // every load of the chunk is issued before the first store: the field of
+  // this thread's site, then both spins' rows (eight per spin and round)
+  const int8_t *srow = w.s + (size_t)(l - 1) * N;
+  const int sv = tid < cnt ? (int)srow[i0 + tid] : 0;
+  decltype(as_global((const F *)nullptr)) lx[2], pr[2];
+  lds_f64 *xd[2], *pd[2];
   for (int sp = 0; sp < 2; ++sp) {
     const int m = w.ne[sp];
-    const F *lx = reinterpret_cast<const F *>(w.LX[sp]) + (size_t)(l - 1) * N * m;
-    double *xd = L.xs + (size_t)(bufi * 2 + sp) * S * mm;
-    double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
-    for (int e = TID - t0; e < cnt * mm; e += nt) {
-      const int r = e / mm, a = e - (e / mm) * mm;
-      xd[e] = a < m ? (double)lx[(size_t)(i0 + r) * m + a] : 0.0;
-      if (!resident && a < m) pd[e] = (double)phi[sp][(size_t)(i0 + r) * m + a];
-    }
+    lx[sp] = as_global(reinterpret_cast<const F *>(w.LX[sp]) + ((size_t)(l - 1) * N + i0) * m);
+    // (a resident block lives in LDS and is not read here: the global view
+    // then points at the left rows, so that no load can leave the buffers)
+    pr[sp] = resident ? lx[sp] : as_global((const F *)phi[sp] + (size_t)i0 * m);
+    xd[sp] = as_lds(L.xs + (size_t)(bufi * 2 + sp) * S * mm);
+    pd[sp] = resident ? nullptr : as_lds(L.ps + (size_t)(bufi * 2 + sp) * S * mm);
   }
-  const int8_t *srow = w.s + (size_t)(l - 1) * N;
-  for (int r = TID - t0; r < cnt; r += nt) {
-    L.fs[bufi * S + r] = srow[i0 + r];
-    L.us[bufi * S + r] = uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)(i0 + r));
-    const int sv = srow[i0 + r];
-    L.dl[(bufi * 2 + 0) * S + r] = sv > 0 ? w.delta_dn_s : w.delta_up_s;
-    L.dl[(bufi * 2 + 1) * S + r] = -sv > 0 ? w.delta_dn_s : w.delta_up_s;
+  int r = tid / mm, a = tid - r * mm;
+  bool first = true;
+  for (int e0 = tid; e0 < tot || first; e0 += 8 * nt) {
+    double xv[2][8], pv[2][8];
+    const int r0 = r, a0 = a;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      const int m = w.ne[sp];
+      r = r0;
+      a = a0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = e0 + u * nt < tot && a < m;
+        xv[sp][u] = ok ? (double)lx[sp][r * m + a] : 0.0;
+        pv[sp][u] = (ok && !resident) ? (double)pr[sp][r * m + a] : 0.0;
+        a += da;
+        r += dr;
+        if (a >= mm) { a -= mm; ++r; }
+      }
+    }
+    if (first) {
+      // the flip uniform and flip factors of this thread's site, while the
+      // loads are in flight
+      if (tid < cnt) {
+        L.us[bufi * S + tid] = uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)(i0 + tid));
+        L.fs[bufi * S + tid] = (int8_t)sv;
+        L.dl[(bufi * 2 + 0) * S + tid] = sv > 0 ? w.delta_dn_s : w.delta_up_s;
+        L.dl[(bufi * 2 + 1) * S + tid] = -sv > 0 ? w.delta_dn_s : w.delta_up_s;
+      }
+      first = false;
+    }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * nt;
+        if (e < tot) {
+          xd[sp][e] = xv[sp][u];
+          if (!resident) pd[sp][e] = pv[sp][u];
+        }
+      }
+  }
+  // sites beyond the threads of the caller (a chunk larger than nt)
+  for (int rr = tid + nt; rr < cnt; rr += nt) {
+    const int v = srow[i0 + rr];
+    L.fs[bufi * S + rr] = (int8_t)v;
+    L.us[bufi * S + rr] = uniform01(w.seed, w.wid, kFlip, sweep, (uint32_t)(l - 1), (uint32_t)(i0 + rr));
+    L.dl[(bufi * 2 + 0) * S + rr] = v > 0 ? w.delta_dn_s : w.delta_up_s;
+    L.dl[(bufi * 2 + 1) * S + rr] = -v > 0 ? w.delta_dn_s : w.delta_up_s;
   }
 }
 
@@ -1336,6 +1700,7 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
   const int cnt = min(S, N - i0);
   const unsigned mask = (unsigned)L.iscal[8 + bufi];
   const int8_t *fs = L.fs + bufi * S;
+  const int tid = TID - t0;
   for (int sp = 0; sp < 2; ++sp) {
     const int m = w.ne[sp];
     auto factor = [&](int r) {
@@ -1345,24 +1710,29 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
     };
     if (resident) {
       if (mask != 0u)
-        for (int e = TID - t0; e < cnt * m; e += nt) {
+        for (int e = tid; e < cnt * m; e += nt) {
           const int r = e / m, a = e - r * m;
           if ((mask >> r) & 1u) phi[sp][(size_t)(i0 + r) * m + a] *= (F)factor(r);
         }
     } else {
-      const double *pd = L.ps + (size_t)(bufi * 2 + sp) * S * mm;
-      for (int e = TID - t0; e < cnt * mm; e += nt) {
-        const int r = e / mm, a = e - r * mm;
+      const lds_f64 *pd = as_lds(L.ps + (size_t)(bufi * 2 + sp) * S * mm);
+      F *dst = phi[sp] + (size_t)i0 * m;
+      const int tot = cnt * mm, dr = nt / mm, da = nt - dr * mm;
+      int r = tid / mm, a = tid - r * mm;
+      for (int e = tid; e < tot; e += nt) {
         if (a < m) {
           double v = pd[e];
           if ((mask >> r) & 1u) v *= factor(r);
-          phi[sp][(size_t)(i0 + r) * m + a] = (F)v;
+          dst[r * m + a] = (F)v;
         }
+        a += da;
+        r += dr;
+        if (a >= mm) { a -= mm; ++r; }
       }
     }
   }
   int8_t *srow = w.s + (size_t)(l - 1) * N;
-  for (int r = TID - t0; r < cnt; r += nt) {
+  for (int r = tid; r < cnt; r += nt) {
     const int8_t f = fs[r];
     srow[i0 + r] = ((mask >> r) & 1u) ? (int8_t)(-f) : f;
   }
@@ -1374,14 +1744,14 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
 template <int T, typename F>
 __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2],
                               bool resident, int mm, ChainAcc &acc) {
-  constexpr bool kReg = T > 0 && T != kDelayed;   // register-tiled inverse
+  constexpr bool kReg = T > 0 && T != kDelayed && T != kMfma;   // register-tiled inverse
   constexpr int TT = kReg ? T : 1;
   const int N = w.N, S = L.S;
   const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
   const int nch = (N + S - 1) / S;
   double M[2 * TT][TT];
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
-  static_assert(T == 0 || T == 1 || T == 2 || T == 4 || T == kDelayed, "chain shape");
+  static_assert(T == 0 || T == 1 || T == 2 || T == 4 || T == kDelayed || T == kMfma, "chain shape");
   if constexpr (T == 0) {
     // column-major copies of the inverses for the chain (A, B are free here)
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -1445,6 +1815,43 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
           double *cu = L.xs + (size_t)bufi * 2 * S * mm;
           if (S <= 8) delayed_epilogue<8>(w, L, cu, mm, S * mm);
           else delayed_epilogue<16>(w, L, cu, mm, S * mm);
+        }
+        flush_chunk(w, L, l, (nch - 1) * S, (nch - 1) & 1, phi, resident, mm, 0, kThreads);
+        SYNC();
+      }
+    } else if constexpr (T == kMfma) {
+      if (!(w.flags & 2)) {
+        const bool uw_lds = L.dgn >= mfma_lds_doubles(w.ne[0], w.ne[1]);
+        const MfBufs mb = mfbufs(w, L.dg, uw_lds);
+        const bool mlds = in_lds(L.Ms0);
+        stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
+        SYNC();
+        for (int c = 0; c < nch; ++c) {
+          const int bufi = c & 1, i0 = c * S;
+          const int cnt = min(S, N - i0);
+          const double *xsb = L.xs + (size_t)bufi * 2 * S * mm;
+          auto side = [&]() {
+            if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+            if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+          };
+          // right rows from the resident block (storage F, row stride Ne) or
+          // the FP64 staging buffer (row stride mm); U, W and the inverses
+          // in LDS or device memory
+          auto run = [&](auto P0, auto P1, int lp0, int lp1) {
+            if (uw_lds) {
+              if (mlds) mf_chunk<lds_f64 *>(w, L, mb, as_lds(L.Ms0), as_lds(L.Ms1), xsb, mm, P0, P1, lp0, lp1, cnt, bufi, acc, side);
+              else mf_chunk<lds_f64 *>(w, L, mb, L.Ms0, L.Ms1, xsb, mm, P0, P1, lp0, lp1, cnt, bufi, acc, side);
+            } else {
+              if (mlds) mf_chunk<double *>(w, L, mb, as_lds(L.Ms0), as_lds(L.Ms1), xsb, mm, P0, P1, lp0, lp1, cnt, bufi, acc, side);
+              else mf_chunk<double *>(w, L, mb, L.Ms0, L.Ms1, xsb, mm, P0, P1, lp0, lp1, cnt, bufi, acc, side);
+            }
+          };
+          if (resident)
+            run(as_lds((const F *)(phi[0] + (size_t)i0 * w.ne[0])), as_lds((const F *)(phi[1] + (size_t)i0 * w.ne[1])),
+                w.ne[0], w.ne[1]);
+          else
+            run(as_lds((const double *)(L.ps + (size_t)(bufi * 2) * S * mm)),
+                as_lds((const double *)(L.ps + (size_t)(bufi * 2 + 1) * S * mm)), mm, mm);
         }
         flush_chunk(w, L, l, (nch - 1) * S, (nch - 1) & 1, phi, resident, mm, 0, kThreads);
         SYNC();
@@ -1906,6 +2313,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(const WalkerDesc *__restri
       case 2: forward_walker<2, F>(w, L, pl, want_aw); break;
       case 4: forward_walker<4, F>(w, L, pl, want_aw); break;
       case kDelayed: forward_walker<kDelayed, F>(w, L, pl, want_aw); break;
+      case kMfma: forward_walker<kMfma, F>(w, L, pl, want_aw); break;
       default: forward_walker<0, F>(w, L, pl, want_aw); break;
     }
   }
@@ -2245,6 +2653,171 @@ __device__ __forceinline__ void fock_propagate_cb(const WalkerDesc &w, int sp, F
   }
 }
 
+// Projections of the addition against a level's basis Q (N x ne, row-major,
+// device memory) when the rows are not cached in registers.  The lanes of a
+// wave run across the columns of a row, two columns per lane (16-byte loads
+// when ne is even), ne2 = ceil(ne / 2) rounded up to a power of two (at most
+// 64) lanes per row, 64 / ne2 rows side by side; above 128 columns a lane
+// takes the pairs c, c + 64, ...  Sixteen row groups are in flight per lane
+// (64 KiB per workgroup), since a level's basis comes from device memory.
+// Sums are taken in a fixed order (xor butterflies, then the four waves in
+// order), so the result does not depend on timing.
+struct QMap {
+  int ne2, rpi, rsub, col, ncq;
+};
+__device__ __forceinline__ QMap qmap(int ne) {
+  QMap q;
+  const int np = (ne + 1) >> 1;
+  q.ne2 = 1;
+  while (q.ne2 < np && q.ne2 < 64) q.ne2 <<= 1;
+  q.rpi = 64 / q.ne2;
+  const int lane = TID & 63;
+  q.rsub = lane / q.ne2;
+  q.col = lane - q.rsub * q.ne2;
+  q.ncq = (np + 63) >> 6;
+  return q;
+}
+// The pair of columns (2 cp, 2 cp + 1) of row i, loaded unconditionally
+// from indices clamped into the block (so that no wait separates the loads
+// of a round); qzero() then zeroes what lies outside.  VEC: one 16-byte load
+// (ne even).
+template <bool VEC>
+__device__ __forceinline__ void qpair(gc_f64 *Q, int ne, int N, int i, int cp, double &x0, double &x1) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(1))) const d2v gc_d2;
+  const int c0 = 2 * cp;
+  const size_t ic = (size_t)min(i, N - 1) * ne;
+  if constexpr (VEC) {
+    const d2v v = *(gc_d2 *)(Q + ic + min(c0, ne - 2));
+    x0 = v[0];
+    x1 = v[1];
+  } else {
+    x0 = Q[ic + min(c0, ne - 1)];
+    x1 = Q[ic + min(c0 + 1, ne - 1)];
+  }
+}
+__device__ __forceinline__ void qzero(int ne, int N, int i, int cp, double &x0, double &x1) {
+  const int c0 = 2 * cp;
+  const bool ok = i < N && c0 < ne;
+  x0 = ok ? x0 : 0.0;
+  x1 = (ok && c0 + 1 < ne) ? x1 : 0.0;
+}
+constexpr int kQR = 16;   // row groups in flight per lane
+// y[a] = sum_i Q[i][a] f[i] for a < ne, into y (LDS)
+template <bool VEC, typename PF>
+__device__ __forceinline__ void fock_qt_t(const double *Qg, int ne, int N, PF f, double *y, double *red) {
+  gc_f64 *Q = as_global(Qg);
+  const QMap mp = qmap(ne);
+  const int wave = TID >> 6, step = 4 * mp.rpi;
+  for (int c = 0; c < mp.ncq; ++c) {
+    const int cp = mp.col + 64 * c;
+    double a0 = 0.0, a1 = 0.0;
+    for (int i0 = wave * mp.rpi; i0 < N; i0 += kQR * step) {
+      double x0[kQR], x1[kQR], fv[kQR];
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) qpair<VEC>(Q, ne, N, i0 + u * step + mp.rsub, cp, x0[u], x1[u]);
+      __builtin_amdgcn_sched_barrier(0);   // every load of the round goes out before the first use
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) qzero(ne, N, i0 + u * step + mp.rsub, cp, x0[u], x1[u]);
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) {
+        const int ii = i0 + u * step + mp.rsub;
+        const double v = (double)f[min(ii, N - 1)];
+        fv[u] = ii < N ? v : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) {
+        a0 = fma(x0[u], fv[u], a0);
+        a1 = fma(x1[u], fv[u], a1);
+      }
+    }
+    // sum over the rows a wave reads side by side, then over the waves
+    for (int m = mp.ne2; m < 64; m <<= 1) {
+      a0 += __shfl_xor(a0, m);
+      a1 += __shfl_xor(a1, m);
+    }
+    if (mp.ne2 == 64) {
+      // 64 lanes per row: the even columns, then the odd ones, through red
+      if (mp.rsub == 0) red[wave * 64 + mp.col] = a0;
+      SYNC();
+      const int cc = 128 * c + 2 * TID;
+      if (TID < 64 && cc < ne) y[cc] = (red[TID] + red[64 + TID]) + (red[128 + TID] + red[192 + TID]);
+      SYNC();
+      if (mp.rsub == 0) red[wave * 64 + mp.col] = a1;
+      SYNC();
+      if (TID < 64 && cc + 1 < ne) y[cc + 1] = (red[TID] + red[64 + TID]) + (red[128 + TID] + red[192 + TID]);
+      SYNC();
+    } else {
+      if (mp.rsub == 0) {
+        red[wave * 64 + mp.col] = a0;
+        red[wave * 64 + 32 + mp.col] = a1;   // col < 32 here
+      }
+      SYNC();
+      if (TID < mp.ne2) {
+        const int cc = 2 * TID;
+        const double s0 = (red[TID] + red[64 + TID]) + (red[128 + TID] + red[192 + TID]);
+        const double s1 = (red[32 + TID] + red[96 + TID]) + (red[160 + TID] + red[224 + TID]);
+        if (cc < ne) y[cc] = s0;
+        if (cc + 1 < ne) y[cc + 1] = s1;
+      }
+      SYNC();
+    }
+  }
+}
+// f[i] -= sum_a Q[i][a] z[a] (z: ne entries in LDS)
+template <bool VEC, typename PF>
+__device__ __forceinline__ void fock_sub_t(const double *Qg, int ne, int N, PF f, const double *z) {
+  gc_f64 *Q = as_global(Qg);
+  const lds_f64 *zl = as_lds(z);
+  const QMap mp = qmap(ne);
+  const int wave = TID >> 6, step = 4 * mp.rpi;
+  double z0[4], z1[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cc = 2 * (mp.col + 64 * c);
+    z0[c] = (c < mp.ncq && cc < ne) ? zl[cc] : 0.0;
+    z1[c] = (c < mp.ncq && cc + 1 < ne) ? zl[cc + 1] : 0.0;
+  }
+  for (int i0 = wave * mp.rpi; i0 < N; i0 += kQR * step) {
+    double sm[kQR];
+#pragma unroll
+    for (int u = 0; u < kQR; ++u) sm[u] = 0.0;
+    for (int c = 0; c < mp.ncq; ++c) {
+      double x0[kQR], x1[kQR];
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) qpair<VEC>(Q, ne, N, i0 + u * step + mp.rsub, mp.col + 64 * c, x0[u], x1[u]);
+      __builtin_amdgcn_sched_barrier(0);   // every load of the round goes out before the first use
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) qzero(ne, N, i0 + u * step + mp.rsub, mp.col + 64 * c, x0[u], x1[u]);
+      const double zc0 = c == 0 ? z0[0] : c == 1 ? z0[1] : c == 2 ? z0[2] : z0[3];
+      const double zc1 = c == 0 ? z1[0] : c == 1 ? z1[1] : c == 2 ? z1[2] : z1[3];
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) sm[u] = fma(x1[u], zc1, fma(x0[u], zc0, sm[u]));
+    }
+    // row sums over the row's lanes (every lane of the row ends with them)
+    for (int m = 1; m < mp.ne2; m <<= 1)
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) sm[u] += __shfl_xor(sm[u], m);
+    if (mp.col == 0)
+#pragma unroll
+      for (int u = 0; u < kQR; ++u) {
+        const int ii = i0 + u * step + mp.rsub;
+        if (ii < N) f[ii] -= sm[u];
+      }
+  }
+}
+
+template <typename PF>
+__device__ __forceinline__ void fock_qt(const double *Q, int ne, int N, PF f, double *y, double *red) {
+  if ((ne & 1) == 0) fock_qt_t<true>(Q, ne, N, f, y, red);
+  else fock_qt_t<false>(Q, ne, N, f, y, red);
+}
+template <typename PF>
+__device__ __forceinline__ void fock_sub(const double *Q, int ne, int N, PF f, const double *z) {
+  if ((ne & 1) == 0) fock_sub_t<true>(Q, ne, N, f, z);
+  else fock_sub_t<false>(Q, ne, N, f, z);
+}
+
 // returns accepted (uniform); *log_abs_r / *sign_r in scal.  F: storage of
 // the propagated column (FP32 for mixed-precision walkers); projections,
 // norms, the stored columns q_i and every ratio are FP64.
@@ -2282,42 +2855,80 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       }
       SYNC();
     } else {
-      for (int t = TID; t < ne * ne; t += kThreads) H[t] = V[t];
-      SYNC();
+      // H = V_i G_{i-1}^T: every row takes the previous level's column
+      // rotations in order, one thread per row (no barrier between them)
       const double *gc = gcb(lvl - 1), *gs = gsb(lvl - 1);
-      for (int r = k; r <= ne - 2; ++r) {
-        const double cc = gc[r], ss = gs[r];
-        for (int row = TID; row < ne; row += kThreads) {
-          const double a = H[row * ne + r], b = H[row * ne + r + 1];
-          H[row * ne + r] = cc * a + ss * b;
-          H[row * ne + r + 1] = -ss * a + cc * b;
+      for (int row = TID; row < ne; row += kThreads) {
+        gc_f64 *vr = as_global(V + (size_t)row * ne);
+        double *hr = H + (size_t)row * ne;
+        for (int a = 0; a < k; ++a) hr[a] = vr[a];
+        double carry = vr[k];
+        // sixteen loads of the row in flight before their rotations
+        for (int r0 = k; r0 <= ne - 2; r0 += 16) {
+          const int nr = min(16, ne - 1 - r0);
+          double b[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) b[u] = u < nr ? vr[r0 + 1 + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (u < nr) {
+              const double cc = gc[r0 + u], ss = gs[r0 + u];
+              hr[r0 + u] = cc * carry + ss * b[u];
+              carry = -ss * carry + cc * b[u];
+            }
         }
-        SYNC();
+        hr[ne - 1] = carry;
       }
+      SYNC();
     }
     double *gc = fgc + (size_t)lvl * mm, *gs = fgs + (size_t)lvl * mm;
-    for (int r = k; r <= ne - 2; ++r) {
-      if (TID == 0) {
-        const double a = H[r * ne + r], b = H[(r + 1) * ne + r];
+    // Givens retriangulation of the Hessenberg part (rows k..ne-1) by wave 0:
+    // the carried row r and the next row r + 1 in registers (lane l owns
+    // columns l, l + 64, ...), the pivot pair broadcast by readlane
+    if (TID < 64 && k <= ne - 2) {
+      const int lane = TID;
+      double carry[4], nxt[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = lane + 64 * q;
+        carry[q] = col < ne ? H[k * ne + col] : 0.0;
+      }
+      for (int r = k; r <= ne - 2; ++r) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = lane + 64 * q;
+          nxt[q] = col < ne ? H[(r + 1) * ne + col] : 0.0;
+        }
+        const int qr = r >> 6, lr = r & 63;
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q == qr) {
+            a = lane_read(carry[q], lr);
+            b = lane_read(nxt[q], lr);
+          }
         const double hh = hypot(a, b);
         double cc = 1.0, ss = 0.0;
         if (hh != 0.0) { cc = a / hh; ss = b / hh; }
-        L.scal[24] = cc;
-        L.scal[25] = ss;
-        gc[r] = cc;
-        gs[r] = ss;
-        gcb(lvl)[r] = cc;
-        gsb(lvl)[r] = ss;
+        if (lane == 0) {
+          gc[r] = cc;
+          gs[r] = ss;
+          gcb(lvl)[r] = cc;
+          gsb(lvl)[r] = ss;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = lane + 64 * q;
+          const double u = carry[q], d = nxt[q];
+          if (col < ne) H[r * ne + col] = cc * u + ss * d;
+          carry[q] = col == r ? 0.0 : -ss * u + cc * d;
+        }
       }
-      SYNC();
-      const double cc = L.scal[24], ss = L.scal[25];
-      for (int col = r + TID; col < ne; col += kThreads) {
-        const double u = H[r * ne + col], d = H[(r + 1) * ne + col];
-        H[r * ne + col] = cc * u + ss * d;
-        H[(r + 1) * ne + col] = -ss * u + cc * d;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = lane + 64 * q;
+        if (col < ne) H[(ne - 1) * ne + col] = carry[q];
       }
-      SYNC();
-      if (TID == 0) H[(r + 1) * ne + r] = 0.0;
     }
     SYNC();
     double *Vp = fVp + (size_t)lvl * mm * mm;
@@ -2335,16 +2946,26 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
     double *Tm = L.B;
     for (int t = TID; t < ne * ne; t += kThreads) Tm[t] = w.Minv[sp][t];
     SYNC();
+    // rows rotated in order, one thread per column (no barrier between them)
     const double *gc = gcb(n - 1), *gs = gsb(n - 1);
-    for (int r = k; r <= ne - 2; ++r) {
-      const double cc = gc[r], ss = gs[r];
-      for (int col = TID; col < ne; col += kThreads) {
-        const double a = Tm[r * ne + col], b = Tm[(r + 1) * ne + col];
-        Tm[r * ne + col] = cc * a + ss * b;
-        Tm[(r + 1) * ne + col] = -ss * a + cc * b;
+    for (int col = TID; col < ne; col += kThreads) {
+      double carry = Tm[k * ne + col];
+      for (int r0 = k; r0 <= ne - 2; r0 += 16) {
+        const int nr = min(16, ne - 1 - r0);
+        double b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) b[u] = u < nr ? Tm[(r0 + 1 + u) * ne + col] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u < nr) {
+            const double cc = gc[r0 + u], ss = gs[r0 + u];
+            Tm[(r0 + u) * ne + col] = cc * carry + ss * b[u];
+            carry = -ss * carry + cc * b[u];
+          }
       }
-      SYNC();
+      Tm[(ne - 1) * ne + col] = carry;
     }
+    SYNC();
     for (int t = TID; t < ne * ne; t += kThreads) {
       const int r = t / ne, c = t % ne;
       Mp[t] = Tm[r * ne + perm_col(c, k, ne)];
@@ -2432,8 +3053,10 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
           if (TID < ne)
             y[TID] = (L.red[TID] + L.red[kFne + TID]) + (L.red[2 * kFne + TID] + L.red[3 * kFne + TID]);
           SYNC();
+        } else if (in_lds(fw)) {
+          fock_qt(Q, ne, N, as_lds(fw), y, L.red);  // y = Q^T w
         } else {
-          gram(Q, ne, fw, 1, N, y, L.red);  // y = Q^T w
+          fock_qt(Q, ne, N, fw, y, L.red);
         }
         if (TID == 0 && ne <= kFne) {
           // the same steps on register copies (ne <= kFne): one LDS round trip
@@ -2491,12 +3114,10 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
               if (a < ne) s += qr[q][a] * z[a];
             if (i < N) fw[i] -= s;
           }
+        } else if (in_lds(fw)) {
+          fock_sub(Q, ne, N, as_lds(fw), z);
         } else {
-          for (int i = TID; i < N; i += kThreads) {
-            double s = 0.0;
-            for (int a = 0; a < ne; ++a) s += Q[(size_t)i * ne + a] * z[a];
-            fw[i] -= s;
-          }
+          fock_sub(Q, ne, N, fw, z);
         }
         SYNC();
       }
@@ -2576,14 +3197,26 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
             gsl[TID] = fgs[(size_t)lvl * mm + TID];
           }
           SYNC();
-          const double *gc = gcl, *gs = gsl;
+          const lds_f64 *gc = as_lds(gcl), *gs = as_lds(gsl);
           const double *q = fq + (size_t)lvl * N;
+          // rows rotated by the level's Givens sequence (the removed column
+          // ends last and is replaced by q_i); sixteen loads of a row are in
+          // flight before its rotations and stores
           for (int i = TID; i < N; i += kThreads) {
             double *row = Q + (size_t)i * ne;
-            for (int r = k; r <= ne - 2; ++r) {
-              const double a = row[r], b = row[r + 1];
-              row[r] = gc[r] * a + gs[r] * b;
-              row[r + 1] = -gs[r] * a + gc[r] * b;
+            double carry = row[k];
+            for (int r0 = k; r0 <= ne - 2; r0 += 16) {
+              const int nr = min(16, ne - 1 - r0);
+              double b[16];
+#pragma unroll
+              for (int u = 0; u < 16; ++u) b[u] = u < nr ? row[r0 + 1 + u] : 0.0;
+#pragma unroll
+              for (int u = 0; u < 16; ++u)
+                if (u < nr) {
+                  const double cc = gc[r0 + u], ss = gs[r0 + u];
+                  row[r0 + u] = cc * carry + ss * b[u];
+                  carry = -ss * carry + cc * b[u];
+                }
             }
             row[ne - 1] = q[i];
           }
@@ -2885,6 +3518,7 @@ hipError_t launch_forward(const WalkerDesc *d, int n, LdsPlan p, int tile, int d
     case 2: return launch_forward_t<2>(d, n, p, do_measure, mixed, st);
     case 4: return launch_forward_t<4>(d, n, p, do_measure, mixed, st);
     case kDelayed: return launch_forward_t<kDelayed>(d, n, p, do_measure, mixed, st);
+    case kMfma: return launch_forward_t<kMfma>(d, n, p, do_measure, mixed, st);
     case 0: return launch_forward_t<0>(d, n, p, do_measure, mixed, st);
     default: return launch_forward_t<-1>(d, n, p, do_measure, mixed, st);
   }

@@ -189,9 +189,11 @@ class LaneServer:
         self.edges = tuple(edges)
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
-        self.lanes = [dict(ctx=c, pending=deque(), active=[], graveyard=[], steps=[]) for c in ctxs]
+        self.lanes = [dict(ctx=c, pending=deque(), active=[], graveyard=[], steps=[], step_active=[]) for c in ctxs]
         self.lock = threading.Lock()
         self.results: dict = {}
+        self.admitted: dict = {}        # rid -> (arrival, admission time)
+        self.sweeps_done: dict = {}     # rid -> sweeps done (also for requests cut off by a deadline)
         self.updates = 0
         self.in_use = 0
         self.n_active = 0
@@ -235,6 +237,8 @@ class LaneServer:
             ln["pending"].popleft()
             w = lecqmc.Walker(ln["ctx"], req.lattice, req.params)
             ln["active"].append([req, w, 0, now, need])
+            with self.lock:
+                self.admitted[req.rid] = (req.arrival, now)
 
     def _retire(self, ln, now):
         keep = []
@@ -252,9 +256,19 @@ class LaneServer:
                 keep.append(entry)
         ln["active"] = keep
 
-    def _lane(self, ln, clock, errors):
+    def _lane(self, ln, clock, errors, deadline=None):
         try:
             while ln["pending"] or ln["active"]:
+                if deadline is not None and clock() >= deadline:
+                    # the window is over: requests still running are cut off
+                    for req, w, done, _, need in ln["active"]:
+                        ln["graveyard"].append([w, need])
+                        with self.lock:
+                            self.sweeps_done[req.rid] = done
+                            self.n_active -= 1
+                    ln["active"] = []
+                    ln["pending"].clear()
+                    break
                 if self.short and ln["graveyard"]:
                     self._free(ln)
                     self.short = False
@@ -268,10 +282,13 @@ class LaneServer:
                 lecqmc.sweep_batch([e[1] for e in ln["active"]], 1, measure=any(e[0].measure for e in ln["active"]))
                 ln["ctx"].synchronize()
                 ln["steps"].append((time.perf_counter() - t0) * 1e3)
+                ln["step_active"].append(len(ln["active"]))
                 n = 0
                 for e in ln["active"]:
                     e[2] += 1
                     n += e[0].lattice.n_sites * e[0].params.L_tau
+                    with self.lock:
+                        self.sweeps_done[e[0].rid] = e[2]
                 with self.lock:
                     self.updates += n
                 self._retire(ln, clock())
@@ -283,9 +300,10 @@ class LaneServer:
         except BaseException as exc:    # reported by run() on the caller's thread
             errors.append(exc)
 
-    def run(self, requests, clock=None) -> dict:
-        """Serve until every request has finished; ``clock`` gives seconds
-        since the start (wall clock by default)."""
+    def run(self, requests, clock=None, deadline=None) -> dict:
+        """Serve until every request has finished, or until ``deadline``
+        seconds (requests still queued or running then are cut off);
+        ``clock`` gives seconds since the start (wall clock by default)."""
         import threading
         lane_of = {}
         for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
@@ -294,7 +312,8 @@ class LaneServer:
         start = time.perf_counter()
         clock = clock or (lambda: time.perf_counter() - start)
         errors = []
-        threads = [threading.Thread(target=self._lane, args=(ln, clock, errors), daemon=True) for ln in self.lanes]
+        threads = [threading.Thread(target=self._lane, args=(ln, clock, errors, deadline), daemon=True)
+                   for ln in self.lanes]
         for t in threads:
             t.start()
         for t in threads:
@@ -306,6 +325,9 @@ class LaneServer:
         wall = time.perf_counter() - start
         lat = [r.latency for r in self.results.values()]
         steps = [x for ln in self.lanes for x in ln["steps"]]
+        # sweep latency as the requests see it: every request resident in a
+        # step waits for that whole step
+        req_sweeps = [x for ln in self.lanes for x, k in zip(ln["steps"], ln["step_active"]) for _ in range(k)]
         pct = lambda v: {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99))} if v else None
         return {
             "requests": len(self.results),
@@ -317,8 +339,78 @@ class LaneServer:
                                                  if lane_of[rid] == k])}
                       for k, ln in enumerate(self.lanes)],
             "step_ms": pct(steps),
+            "request_sweep_latency_ms": pct(req_sweeps),
             "request_latency_s": pct(lat),
+            "admitted": len(self.admitted),
+            "queue_wait_s": pct([a - r for r, a in self.admitted.values()]),
+            "sweeps_done": int(sum(self.sweeps_done.values())),
         }
+
+
+_SQUARE = {}
+
+
+def serving_stream(window, rate=50.0, seed=0, dtau=0.05, n_stab=10, measure=False):
+    """The serving workload's requests that arrive within ``window`` seconds:
+    Poisson arrivals at ``rate`` per second (seeded exponential gaps), L x L
+    periodic square lattices with L uniform over the even numbers 16..128
+    (N up to 16384), N_up = N_dn uniform in 4..64, U uniform in [2, 8], beta
+    uniform in [4, 32] rounded to a whole number of stabilisation blocks
+    (dtau = 0.05, a QR every 10 slices), 100..1000 sweeps, seed = request
+    id."""
+    from . import workloads as W
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > window:
+            return out
+        Ls = int(rng.choice(np.arange(16, 129, 2)))
+        ne = int(rng.integers(4, 65))
+        U = round(float(rng.uniform(2.0, 8.0)), 3)
+        blocks = max(1, int(round(float(rng.uniform(4.0, 32.0)) / (dtau * n_stab))))
+        rid = len(out)
+        par = W.Params(U=U, beta=round(blocks * dtau * n_stab, 9), dtau=dtau, n_stab=n_stab, n_up=ne, n_dn=ne,
+                       seed=1000 + rid, walker_id=rid)
+        if Ls not in _SQUARE:
+            _SQUARE[Ls] = W.square_lattice(Ls)
+        out.append(Request(rid, _SQUARE[Ls], par, int(rng.integers(100, 1001)), t, measure=measure))
+
+
+def serving_window(window, rate=50.0, seed=0, budget_bytes=200 * 2**30, lanes=5, log=None) -> dict:
+    """Serve the serving workload's stream for ``window`` seconds on lane
+    servers (one context per lane) and report what the window achieved:
+    offered, admitted and finished requests, aggregate HS-field updates per
+    second, the sweep latency the resident requests saw (p50/p99), the wait
+    from arrival to admission, and the highest arrival rate the measured
+    throughput sustains (throughput / mean work of a request, the mean taken
+    over 20000 draws of the request distribution)."""
+    reqs = serving_stream(window, rate, seed)
+    draws = serving_stream(20000.0 / rate, rate, seed + 1)
+    mean_work = float(np.mean([r.lattice.n_sites * r.params.L_tau * r.sweeps for r in draws]))
+    edges = tuple(0.05 * 10.0 ** k for k in range(lanes - 1))
+    ctxs = [lecqmc.Context(0) for _ in range(lanes)]
+    srv = LaneServer(ctxs, budget_bytes, edges=edges)
+    if log:
+        srv.on_finish = lambda r: log(f"serving: request {r.rid} finished, latency {r.latency:.1f} s")
+    rep = srv.run(reqs, deadline=window)
+    for c in ctxs:
+        c.close()
+    thr = rep["updates_per_s"]
+    return {
+        "window_s": window, "offered_rate_per_s": rate, "offered": len(reqs), "admitted": rep["admitted"],
+        "finished": rep["requests"], "sweeps_done": rep["sweeps_done"],
+        "updates_per_s": thr, "unit": "HS-field updates/s",
+        "request_sweep_latency_ms": rep["request_sweep_latency_ms"], "queue_wait_s": rep["queue_wait_s"],
+        "request_latency_s": rep["request_latency_s"], "lanes": rep["lanes"], "lane_edges_s": list(edges),
+        "budget_gib": budget_bytes / 2**30,
+        "mean_request_updates": mean_work,
+        "sustainable_rate_per_s": thr / mean_work if mean_work > 0 else 0.0,
+        "config": "Poisson arrivals at 50/s; L x L periodic square, L even in 16..128; Ne per spin 4..64; U 2..8; "
+                  "beta 4..32 (whole QR blocks, dtau=0.05, QR every 10 slices); 100..1000 sweeps; FP64; "
+                  "admitted by device footprint; no estimators; requests still queued or running at the end of "
+                  "the window are cut off",
+    }
 
 
 def poisson_stream(n, rate, seed=0, lattices=(8, 12, 16, 24), ne_range=(2, 16), U_range=(2.0, 8.0),

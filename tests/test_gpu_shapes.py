@@ -18,7 +18,7 @@ from paper_2601_08552_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-10
-TILES = (1, 2, 4, 0, 9)
+TILES = (1, 2, 4, 0, 9, 10)
 CHUNKS = (4, 8, 16, 32)
 
 
@@ -63,7 +63,7 @@ def _matches_oracle(g, o):
 
 
 def test_every_shape_follows_the_oracle(lq):
-    """All 19 valid (tile, chunk) shapes on one walker (Ne = 5 + 3, ragged last
+    """All 20 valid (tile, chunk) shapes on one walker (Ne = 5 + 3, ragged last
     chunk: N = 36) against the oracle's sweep."""
     lat, par = _case(5, 3)
     o = oracle.Walker(lat, par)
@@ -73,7 +73,9 @@ def test_every_shape_follows_the_oracle(lq):
         for c in CHUNKS:
             print(f"shape tile={t} chunk={c}", flush=True)
             g = lq.Walker(ctx, lat, par)
-            if t == 9 and c > 16:          # the delayed chain takes at most 16 sites per chunk
+            if (t == 9 and c > 16) or (t == 10 and c != 16):
+                # the delayed chain takes at most 16 sites per chunk, the
+                # matrix-core chain exactly one 16-wide tile
                 with pytest.raises(lq.LecqmcError) as e:
                     g.set_shape(t, c)
                 assert e.value.code == lq.EINVAL
@@ -145,7 +147,7 @@ def test_autotune_keeps_the_chain(lq):
     for (tile, chunk, ms), w, (nu, nd, _) in zip(res, ws, specs):
         assert (tile, chunk) == w.shape
         assert tile in TILES and chunk in CHUNKS and ms > 0
-        assert tile in (0, 9) or max(nu, nd) <= 8 * tile
+        assert tile in (0, 9, 10) or max(nu, nd) <= 8 * tile
     for w, (st, tw, stats, meas) in zip(ws, before):
         for x, y in zip(w.state(), st):
             assert np.array_equal(np.asarray(x), np.asarray(y))
@@ -165,11 +167,12 @@ def test_autotune_keeps_the_chain(lq):
 
 
 def test_mixed_shape_batch_equals_alone(lq):
-    """Walkers with tiles 1, 2, 4, 0 and 9 (delayed) and different chunks in one batch
+    """Walkers with tiles 1, 2, 4, 0, 9 (delayed) and 10 (matrix cores) and different chunks in one batch
     (one launch that dispatches each walker's shape) against the same
     walkers swept alone."""
     specs = [(3, 2, 6, (1, 32)), (11, 7, 6, (2, 8)), (20, 18, 6, (4, 16)), (36, 4, 8, (0, 4)), (6, 6, 8, (4, 32)),
-             (13, 9, 6, (0, 8)), (27, 30, 6, (4, 8)), (12, 5, 6, (9, 16)), (40, 33, 8, (9, 8))]
+             (13, 9, 6, (0, 8)), (27, 30, 6, (4, 8)), (12, 5, 6, (9, 16)), (40, 33, 8, (9, 8)),
+             (21, 19, 6, (10, 16)), (5, 3, 6, (10, 16)), (44, 37, 8, (10, 16))]
     ctx = lq.Context(0)
     alone, batch = [], []
     for (nu, nd, Ls, shp) in specs:
@@ -191,7 +194,7 @@ def test_mixed_shape_batch_equals_alone(lq):
     ctx.close()
 
 
-@pytest.mark.parametrize("big_shape", [(0, 4), (9, 16)])
+@pytest.mark.parametrize("big_shape", [(0, 4), (9, 16), (10, 16)])
 def test_large_ne_in_a_batch(lq, big_shape):
     """A walker with Ne > 64 (work matrices in device memory for the whole
     launch) batched with walkers that alone keep them in LDS: every walker
@@ -238,4 +241,22 @@ def test_batch_moves_matrices_out_of_lds(lq):
     lq.sweep_batch(batch, 2, measure=True)
     for a, b in zip(alone, batch):
         assert _same(a, b)
+    ctx.close()
+
+
+@pytest.mark.parametrize("ne", [(1, 1), (8, 8), (16, 15), (17, 2), (32, 32), (33, 31), (48, 0), (64, 64)])
+def test_matrix_core_chain_follows_the_oracle(lq, ne):
+    """The matrix-core chain (tile 10) on tile edges of Ne (1, 15/16/17,
+    32/33, 48 with an empty spin, 64) and a ragged last chunk (N = 36 or 100):
+    the oracle's chain, weights and estimators."""
+    Ls = 6 if max(ne) <= 20 else 10
+    lat, par = _case(ne[0], ne[1], Ls=Ls, beta=1.0, seed=90 + ne[0])
+    o = oracle.Walker(lat, par)
+    o.sweep(2, measure=True)
+    ctx = lq.Context(0)
+    g = lq.Walker(ctx, lat, par)
+    g.set_shape(10, 16)
+    print(f"tile 10, Ne = {ne}", flush=True)
+    g.sweep(2, measure=True)
+    _matches_oracle(g, o)
     ctx.close()

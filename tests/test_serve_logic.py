@@ -171,3 +171,22 @@ def test_lane_leaving_frees_its_retired_walkers(monkeypatch):
     th.join(timeout=20.0)
     assert not th.is_alive(), f"server hung: in_use={srv.in_use}, graveyards={[len(l['graveyard']) for l in srv.lanes]}"
     assert out["rep"]["requests"] == 2 and srv.in_use == 0 and _Walker.live == 0
+
+
+def test_lanes_stop_at_the_deadline(monkeypatch):
+    """A serving window: requests still running or queued when the deadline
+    passes are cut off, their walkers freed, and the report counts what was
+    admitted and done."""
+    monkeypatch.setattr(serve.lecqmc, "Walker", _LaneWalker)
+    monkeypatch.setattr(serve.lecqmc, "sweep_batch", _lane_sweep)
+    monkeypatch.setattr(serve.lecqmc, "footprint_bytes", lambda lat, par: 1000 + lat.n_sites)
+    _Walker.live = 0
+    reqs = serve.poisson_stream(40, rate=200.0, seed=3, lattices=(4, 6, 48), ne_range=(1, 4),
+                                beta_range=(0.5, 1.0), sweeps_range=(200, 400))
+    srv = serve.LaneServer([_LaneCtx(0.002), _LaneCtx(0.01)], budget_bytes=10**9, edges=(1e-3,))
+    t0 = time.perf_counter()
+    rep = srv.run(reqs, deadline=0.5)
+    assert time.perf_counter() - t0 < 5.0
+    assert _Walker.live == 0 and srv.in_use == 0
+    assert 0 < rep["admitted"] <= len(reqs) and rep["requests"] < len(reqs)
+    assert rep["sweeps_done"] > 0 and rep["request_sweep_latency_ms"] is not None
