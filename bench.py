@@ -58,6 +58,22 @@ def algorithmic_bytes_forward(N, ne_up, ne_dn, L, nstab):
     return b + 2 * L * N
 
 
+def measured_traffic(kernel_src, pmc_json):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counters (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's
+    readings), or None when the kernel source changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(pmc_json))
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("src_sha256") != sha:
+        return None
+    kib = rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + rec["write_kib_per_dispatch"] * rec["write_scale"]
+    return kib * 1024.0
+
+
 def note(msg):
     """Progress on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -146,6 +162,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the headline batch (profiling of other legs)")
     ap.add_argument("--no-dilute", action="store_true", help="skip the 32x32 dilute-gas objects")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-flat", action="store_true", help="skip the 128-walker flat-band batch")
@@ -167,8 +184,16 @@ def main():
     # ------------------------------------------------------------------
     # headline: the 256-walker uneven batch
     # ------------------------------------------------------------------
-    note("uneven batch: creating 256 walkers")
     cfg = W.config_batched(256)
+    out = headline(args, cfg) if not args.no_uneven else {"metric": METRIC, "value": None, "note": "--no-uneven"}
+    run_legs(args, cfg, out)
+    print(json.dumps(out), flush=True)
+
+
+def headline(args, cfg):
+    import torch
+    from paper_2601_08552_amd import lecqmc
+    note("uneven batch: creating 256 walkers")
     gs = torch.cuda.Stream()
     gctx = lecqmc.Context(0, stream=gs)
     ws = [lecqmc.Walker(gctx, lat, par) for lat, par in cfg]
@@ -247,10 +272,19 @@ def main():
                              "walker (the dependent flip chain), not as long as its bytes take"},
         "stats_walker0": {k: st0[k] for k in ("logw_drift", "max_wrap_err", "qr_shifted")},
     }
+    traffic = measured_traffic(os.path.join(ROOT, "paper_2601_08552_amd", "csrc", "lecqmc_kernels.hip"),
+                               os.path.join(ROOT, "profiles", "k_forward_batched256_pmc.json"))
+    out["roofline"]["traffic"] = traffic
     for w in ws:
         w.close()
     gctx.close()
+    return out
 
+
+def run_legs(args, cfg, out):
+    import torch
+    from paper_2601_08552_amd import lecqmc
+    from paper_2601_08552_amd import workloads as W
     ctx = lecqmc.Context(0, stream=torch.cuda.current_stream())
     stream = torch.cuda.current_stream()
 
@@ -358,7 +392,6 @@ def main():
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
         note(f"cpu baseline: the oracle on {procs} host cores")
         out["cpu_baseline"] = cpu_baseline(cfg, procs)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
