@@ -19,6 +19,8 @@ _SRC = os.path.join(_HERE, "lecqmc_oracle.c")
 NO_FOCK = 1
 NO_FLIPS = 2
 S_FLIP, S_SWAP_K, S_SWAP_J, S_SWAP_ACC, S_INIT_FIELD, S_INIT_OCC = 1, 2, 3, 4, 5, 6
+S_CP_FIELD, S_CP_COMB = 7, 8
+CP_IMPORTANCE, CP_FREE = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -83,6 +85,12 @@ def lib():
         L.orc_uniform.restype = C.c_double
         L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_cp_create.restype = vp
+        L.orc_cp_create.argtypes = [C.POINTER(_Lat), C.POINTER(_Par), vp, vp, C.c_int32, C.c_int32, C.c_int32]
+        L.orc_cp_destroy.argtypes = [vp]
+        L.orc_cp_run.argtypes = [vp, C.c_uint32, C.POINTER(C.c_double)]
+        L.orc_cp_walker.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+        L.orc_cp_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -224,3 +232,79 @@ class Walker:
         st = Stats()
         self._chk(lib().orc_get_stats(self.h, C.byref(st)))
         return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+
+class CPWalk:
+    """Constrained-path inner walk of one Fock state (SM Sec. VI): a
+    population of random walkers whose weights estimate R(eta) =
+    E_s[prod_sigma det(P^T B(s) P)] / W_T(eta) under the phaseless cut."""
+
+    def __init__(self, lat, par, occ_up, occ_dn, n_walkers, mode=CP_IMPORTANCE, pc_every=0):
+        self._w = Walker.__new__(Walker)   # reuse Walker's marshalling of lattice and parameters
+        self._keep = []
+
+        def arr(x, dt):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        bi, bj, bc = arr(lat.bond_i, np.int32), arr(lat.bond_j, np.int32), arr(lat.bond_color, np.int32)
+        bh, on, sub = arr(lat.bond_h, np.float64), arr(lat.onsite, np.float64), arr(lat.sublattice, np.int32)
+        P = lambda a, t: C.cast(a.ctypes.data, C.POINTER(t)) if a is not None else C.POINTER(t)()
+        self._lat = _Lat(lat.n_sites, lat.n_bonds, lat.n_colors, P(bi, C.c_int32), P(bj, C.c_int32),
+                         P(bc, C.c_int32), P(bh, C.c_double), P(on, C.c_double), P(sub, C.c_int32),
+                         lat.n_sublattices if sub is not None else 1, lat.n_cells)
+        self._par = _Par(par.U, par.beta, par.dtau, par.n_stab, par.n_up, par.n_dn, par.seed,
+                         par.walker_id, par.flags, par.wrap_tol)
+        ou, od = arr(occ_up, np.int32), arr(occ_dn, np.int32)
+        self.N, self.L, self.nw = lat.n_sites, par.L_tau, n_walkers
+        h = lib().orc_cp_create(C.byref(self._lat), C.byref(self._par), _ptr(ou), _ptr(od), n_walkers, mode,
+                                pc_every)
+        if not h:
+            raise ValueError(lib().orc_last_error().decode())
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_cp_destroy(self.h)
+            self.h = None
+
+    def run(self, tag=0):
+        """One inner walk from Phi = P_eta; returns log of the estimate of R(eta)."""
+        lr = C.c_double()
+        if lib().orc_cp_run(self.h, tag, C.byref(lr)) != 0:
+            raise RuntimeError(lib().orc_last_error().decode())
+        return lr.value
+
+    def walker(self, a):
+        """(log weight, sum of log p of its draws, field path [L][N]) of slot a."""
+        lw, lq = C.c_double(), C.c_double()
+        f = np.zeros((self.L, self.N), dtype=np.int8)
+        if lib().orc_cp_walker(self.h, a, C.byref(lw), C.byref(lq), f.ctypes.data) != 0:
+            raise RuntimeError(lib().orc_last_error().decode())
+        return lw.value, lq.value, f
+
+    def stats(self):
+        lp, cuts, alive = C.c_double(), C.c_int64(), C.c_int32()
+        lib().orc_cp_stats(self.h, C.byref(lp), C.byref(cuts), C.byref(alive))
+        return {"log_pc": lp.value, "cuts": cuts.value, "alive": alive.value}
+
+
+def cp_partition_ratio(lat, par, n_eta, sweeps_between, n_walkers, mode=CP_IMPORTANCE, pc_every=0, burn=5):
+    """Two-stage estimate of Z / Z_0 = sum_eta W_T(eta) R(eta) / sum_eta W_T(eta)
+    (SM Sec. VI): the outer chain is the LEC-QMC chain at U = 0, whose Fock
+    moves sample eta with probability W_T(eta) / Z_0; each sampled eta gets
+    one inner walk.  Returns the per-eta estimates of R(eta)."""
+    import dataclasses
+    p0 = dataclasses.replace(par, U=0.0, flags=NO_FLIPS)
+    outer = Walker(lat, p0)
+    outer.sweep(burn)
+    rs = []
+    for t in range(n_eta):
+        _, ou, od, _ = outer.state()
+        walk = CPWalk(lat, par, ou, od, n_walkers, mode, pc_every)
+        rs.append(np.exp(walk.run(tag=t)))
+        outer.sweep(sweeps_between)
+    return np.array(rs)

@@ -1126,3 +1126,312 @@ int64_t orc_obs_size(const orc_walker *w) { return w->nobs; }
 int orc_measure(const orc_walker *w, double *out) { memcpy(out, w->obs, sizeof(double) * w->nobs); return 0; }
 int orc_reset_measure(orc_walker *w) { memset(w->obs, 0, sizeof(double) * w->nobs); return 0; }
 int orc_get_stats(const orc_walker *w, orc_stats *st) { *st = w->st; return 0; }
+
+/* ======================================================================== */
+/* Constrained-path (phaseless) LEC-QMC, SM Sec. VI.                         */
+/*                                                                          */
+/* Two-stage sampling: the outer chain draws Fock states eta with the       */
+/* trial weight W_T(eta) = <eta| e^{-beta H_0} |eta> (the LEC-QMC chain of a */
+/* walker with U = 0, driven by orc_sweep); for one eta the inner branching */
+/* random walk estimates                                                    */
+/*   R(eta) = E_s[ prod_sigma det(P^T B^sigma(s) P) ] / W_T(eta),            */
+/* s uniform over the Ising fields (P(s) = 2^{-N L}), as the telescoping     */
+/* product of overlap ratios O_T(tau_l) / O_T(tau_{l-1}) with the backward   */
+/* trial state <psi(tau_l)| = <eta| e^{-(beta - tau_l) H_0}.                 */
+/* H_0 is the one-body part (checkerboard hopping and onsite energies), so   */
+/* B_l(s) = E_K D0 F_l(s), F_l(s) = diag(exp(sigma lambda s_{l,i})).          */
+/* Across E_K D0 the overlap matrix X^T Phi is unchanged (the trial state    */
+/* moves back by the same factor), so each slice's ratio is the product of   */
+/* its site-by-site rank-1 ratios                                           */
+/*   r_sigma(s) = 1 + (e^{sigma lambda s} - 1) [Phi (X^T Phi)^{-1} X^T]_ii,  */
+/* updated sequentially (Sherman-Morrison) as the fields are drawn.          */
+/* Phaseless constraint: a factor max(0, r) (the Hubbard fields are real, so */
+/* the real part is the ratio itself); a walker whose factor is 0 is dead.   */
+/* Stabilisation: the walker Phi = U_R D_R is replaced by U_R (thin QR) at   */
+/* every block end and the trial state by the QR'd block boundary state U_L  */
+/* of the H_0 left stack; the scales cancel in every ratio.                  */
+/* Field sampling (mode):                                                    */
+/*   ORC_CP_IMPORTANCE: s drawn with p(s) = P(s) max(0, r(s)) / N_i, weight  */
+/*     times N_i = sum_s P(s) max(0, r(s)) (the walker-dependent, site by    */
+/*     site sampling probability);                                          */
+/*   ORC_CP_FREE: s drawn from P(s), weight times max(0, r(s)).              */
+/* Population control (every pc_every slices, 0 = never): a comb over the   */
+/* cumulative weights with one uniform draw; every copy carries the mean    */
+/* weight, whose log is accumulated into the estimator.                     */
+/* ======================================================================== */
+struct orc_cp {
+  orc_walker *tw;            /* U = 0 walker: tables, eta, H_0 left stack */
+  double lambda;             /* Ising coupling of the interacting propagator */
+  int nw, mode, pc_every, N, L;
+  int ne[2];
+  uint64_t seed;
+  double *Phi[2];            /* [nw][N][ne] */
+  double *Minv[2];           /* [nw][ne][ne] */
+  double *logw;              /* [nw], -INFINITY = dead */
+  double *logq;              /* [nw] sum of log p(s) of the drawn fields (importance mode) */
+  int8_t *s;                 /* [nw][L][N] drawn field path */
+  double log_pc;             /* sum of log(mean weight) over the population controls */
+  int64_t cuts;              /* site updates at which a walker died */
+};
+
+static void cp_free_walkers(orc_cp *c) {
+  for (int sp = 0; sp < 2; ++sp) { free(c->Phi[sp]); free(c->Minv[sp]); c->Phi[sp] = c->Minv[sp] = NULL; }
+  free(c->logw); free(c->logq); free(c->s);
+  c->logw = c->logq = NULL; c->s = NULL;
+}
+
+orc_cp *orc_cp_create(const orc_lattice *lat, const orc_params *par, const int32_t *occ_up,
+                      const int32_t *occ_dn, int32_t n_walkers, int32_t mode, int32_t pc_every) {
+  if (!lat || !par || !occ_up || !occ_dn) { set_err("null argument"); return NULL; }
+  if (n_walkers <= 0 || (mode != ORC_CP_IMPORTANCE && mode != ORC_CP_FREE) || pc_every < 0) {
+    set_err("bad walker count, mode or control interval"); return NULL;
+  }
+  orc_params p0 = *par;
+  p0.U = 0.0;
+  p0.flags = ORC_NO_FLIPS | ORC_NO_FOCK;
+  orc_walker *tw = orc_create(lat, &p0, NULL, occ_up, occ_dn);
+  if (!tw) return NULL;
+  orc_cp *c = calloc(1, sizeof *c);
+  c->tw = tw;
+  c->lambda = acosh(exp(par->dtau * par->U / 2.0));
+  c->nw = n_walkers; c->mode = mode; c->pc_every = pc_every;
+  c->N = tw->N; c->L = tw->L; c->ne[0] = tw->ne[0]; c->ne[1] = tw->ne[1];
+  c->seed = par->seed;
+  for (int sp = 0; sp < 2; ++sp) {
+    size_t m = c->ne[sp] ? (size_t)c->ne[sp] : 1;
+    c->Phi[sp] = malloc(sizeof(double) * (size_t)n_walkers * c->N * m);
+    c->Minv[sp] = malloc(sizeof(double) * (size_t)n_walkers * m * m);
+  }
+  c->logw = malloc(sizeof(double) * n_walkers);
+  c->logq = malloc(sizeof(double) * n_walkers);
+  c->s = malloc((size_t)n_walkers * c->L * c->N);
+  return c;
+}
+
+void orc_cp_destroy(orc_cp *c) {
+  if (!c) return;
+  cp_free_walkers(c);
+  orc_destroy(c->tw);
+  free(c);
+}
+
+/* fresh (X^T Phi)^{-1} of walker a, spin sp */
+static void cp_fresh_inverse(orc_cp *c, int a, int sp, const double *X) {
+  int N = c->N, m = c->ne[sp];
+  if (m == 0) return;
+  double *M = malloc(sizeof(double) * m * m);
+  xty(X, c->Phi[sp] + (size_t)a * N * m, N, m, M);
+  double la; int sg;
+  lu_inverse(M, m, c->Minv[sp] + (size_t)a * m * m, &la, &sg);
+  free(M);
+}
+
+/* comb: nw copies chosen at the positions (j + xi) W / nw of the cumulative
+ * weights; every copy carries weight W / nw (log accumulated in log_pc) */
+static void cp_comb(orc_cp *c, double xi) {
+  int nw = c->nw, N = c->N, L = c->L;
+  double mx = -INFINITY;
+  for (int a = 0; a < nw; ++a) if (c->logw[a] > mx) mx = c->logw[a];
+  if (mx == -INFINITY) return;  /* every walker dead: nothing to resample */
+  double *cum = malloc(sizeof(double) * nw);
+  double W = 0.0;
+  for (int a = 0; a < nw; ++a) { W += exp(c->logw[a] - mx); cum[a] = W; }
+  int *pick_of = malloc(sizeof(int) * nw);
+  int a = 0;
+  for (int j = 0; j < nw; ++j) {
+    double t = ((double)j + xi) * W / (double)nw;
+    while (a < nw - 1 && cum[a] <= t) ++a;
+    /* rounding can carry t onto a dead walker's empty interval: take the
+     * nearest live walker instead */
+    int b = a;
+    while (b > 0 && c->logw[b] == -INFINITY) --b;
+    while (b < nw - 1 && c->logw[b] == -INFINITY) ++b;
+    pick_of[j] = b;
+  }
+  double *Phi[2], *Minv[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    size_t m = c->ne[sp] ? (size_t)c->ne[sp] : 1;
+    Phi[sp] = malloc(sizeof(double) * (size_t)nw * N * m);
+    Minv[sp] = malloc(sizeof(double) * (size_t)nw * m * m);
+    for (int j = 0; j < nw; ++j) {
+      memcpy(Phi[sp] + (size_t)j * N * m, c->Phi[sp] + (size_t)pick_of[j] * N * m, sizeof(double) * N * m);
+      memcpy(Minv[sp] + (size_t)j * m * m, c->Minv[sp] + (size_t)pick_of[j] * m * m, sizeof(double) * m * m);
+    }
+    free(c->Phi[sp]); free(c->Minv[sp]);
+    c->Phi[sp] = Phi[sp]; c->Minv[sp] = Minv[sp];
+  }
+  int8_t *s = malloc((size_t)nw * L * N);
+  double *lq = malloc(sizeof(double) * nw);
+  for (int j = 0; j < nw; ++j) {
+    memcpy(s + (size_t)j * L * N, c->s + (size_t)pick_of[j] * L * N, (size_t)L * N);
+    lq[j] = c->logq[pick_of[j]];
+  }
+  free(c->s); c->s = s;
+  free(c->logq); c->logq = lq;
+  c->log_pc += mx + log(W / (double)nw);
+  for (int j = 0; j < nw; ++j) c->logw[j] = 0.0;
+  free(cum); free(pick_of);
+}
+
+/* one site update of walker a at slice l, site i (fields drawn here) */
+static void cp_site(orc_cp *c, int a, int l, int i, uint32_t tag, double *const X[2], double *u, double *v) {
+  int N = c->N;
+  double g[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    int m = c->ne[sp];
+    const double *Mi = c->Minv[sp] + (size_t)a * m * m;
+    const double *ph = c->Phi[sp] + ((size_t)a * N + i) * m;
+    double acc = 0.0;
+    for (int p = 0; p < m; ++p) {
+      double t = 0.0;
+      for (int q = 0; q < m; ++q) t += Mi[p * m + q] * X[sp][(size_t)i * m + q];
+      acc += ph[p] * t;
+    }
+    g[sp] = acc;   /* [Phi (X^T Phi)^{-1} X^T]_ii */
+  }
+  double f[2];  /* max(0, r(s)) for s = +1, -1; r = product over spins */
+  for (int t = 0; t < 2; ++t) {
+    double sv = t == 0 ? 1.0 : -1.0;
+    double prod = 1.0;
+    for (int sp = 0; sp < 2; ++sp) {
+      double sigma = sp == 0 ? 1.0 : -1.0;
+      prod *= 1.0 + (exp(sigma * c->lambda * sv) - 1.0) * g[sp];
+    }
+    f[t] = prod > 0.0 ? prod : 0.0;
+  }
+  double x = orc_uniform(c->seed, (uint64_t)a, ORC_S_CP_FIELD, tag, (uint32_t)(l - 1), (uint32_t)i);
+  int t;
+  double factor;
+  if (c->mode == ORC_CP_IMPORTANCE) {
+    double Ni = 0.5 * f[0] + 0.5 * f[1];
+    if (Ni == 0.0) { c->logw[a] = -INFINITY; c->cuts++; return; }
+    double p_plus = 0.5 * f[0] / Ni;
+    t = x < p_plus ? 0 : 1;
+    factor = Ni;
+    c->logq[a] += log(t == 0 ? p_plus : 1.0 - p_plus);
+  } else {
+    t = x < 0.5 ? 0 : 1;
+    factor = f[t];
+    if (factor == 0.0) { c->logw[a] = -INFINITY; c->cuts++; return; }
+  }
+  double sv = t == 0 ? 1.0 : -1.0;
+  c->s[((size_t)a * c->L + (l - 1)) * N + i] = (int8_t)(t == 0 ? 1 : -1);
+  c->logw[a] += log(factor);
+  /* apply F_i(s) to the walker: Phi[i,:] *= 1 + delta, Sherman-Morrison on (X^T Phi)^{-1} */
+  for (int sp = 0; sp < 2; ++sp) {
+    int m = c->ne[sp];
+    if (m == 0) continue;
+    double sigma = sp == 0 ? 1.0 : -1.0;
+    double delta = exp(sigma * c->lambda * sv) - 1.0;
+    double rs = 1.0 + delta * g[sp];
+    double *Mi = c->Minv[sp] + (size_t)a * m * m;
+    double *ph = c->Phi[sp] + ((size_t)a * N + i) * m;
+    for (int p = 0; p < m; ++p) {
+      double acc = 0.0;
+      for (int q = 0; q < m; ++q) acc += Mi[p * m + q] * X[sp][(size_t)i * m + q];
+      u[p] = acc;
+    }
+    for (int q = 0; q < m; ++q) {
+      double acc = 0.0;
+      for (int p = 0; p < m; ++p) acc += ph[p] * Mi[p * m + q];
+      v[q] = acc;
+    }
+    double cc = delta / rs;
+    for (int p = 0; p < m; ++p)
+      for (int q = 0; q < m; ++q) Mi[p * m + q] -= cc * u[p] * v[q];
+    for (int p = 0; p < m; ++p) ph[p] *= 1.0 + delta;
+  }
+}
+
+int orc_cp_run(orc_cp *c, uint32_t tag, double *log_r) {
+  if (!c || !log_r) { set_err("null argument"); return -1; }
+  orc_walker *tw = c->tw;
+  int N = c->N, n = tw->nblk, nw = c->nw;
+  double *LS[2], *X[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    size_t m = c->ne[sp] ? (size_t)c->ne[sp] : 1;
+    LS[sp] = left_stack(tw, sp);         /* H_0 left stack (lambda = 0) */
+    X[sp] = malloc(sizeof(double) * N * m);
+    for (int a = 0; a < nw; ++a) fill_P(tw, sp, c->Phi[sp] + (size_t)a * N * m);
+  }
+  for (int a = 0; a < nw; ++a) { c->logw[a] = 0.0; c->logq[a] = 0.0; }
+  memset(c->s, 0, (size_t)nw * c->L * N);
+  c->log_pc = 0.0;
+  c->cuts = 0;
+  int mmax = c->ne[0] > c->ne[1] ? c->ne[0] : c->ne[1];
+  double *u = malloc(sizeof(double) * (mmax + 1)), *v = malloc(sizeof(double) * (mmax + 1));
+  for (int k = 1; k <= n; ++k) {
+    for (int sp = 0; sp < 2; ++sp) {
+      int m = c->ne[sp];
+      memcpy(X[sp], LS[sp] + (size_t)(k - 1) * N * m, sizeof(double) * (size_t)N * m);
+      for (int a = 0; a < nw; ++a)
+        if (c->logw[a] > -INFINITY) cp_fresh_inverse(c, a, sp, X[sp]);
+    }
+    for (int l = block_first(tw, k); l <= block_last(tw, k); ++l) {
+      /* D0 on the walkers, D0^{-1} on the trial state: the flip point of slice l */
+      for (int sp = 0; sp < 2; ++sp) {
+        int m = c->ne[sp];
+        diag_left(tw, X[sp], m, l, sp, 1);
+        for (int a = 0; a < nw; ++a)
+          if (c->logw[a] > -INFINITY) diag_left(tw, c->Phi[sp] + (size_t)a * N * m, m, l, sp, 0);
+      }
+      for (int a = 0; a < nw; ++a)
+        for (int i = 0; i < N && c->logw[a] > -INFINITY; ++i) cp_site(c, a, l, i, tag, X, u, v);
+      for (int sp = 0; sp < 2; ++sp) {
+        int m = c->ne[sp];
+        ekinvT_left(tw, X[sp], m);
+        for (int a = 0; a < nw; ++a)
+          if (c->logw[a] > -INFINITY) ek_left(tw, c->Phi[sp] + (size_t)a * N * m, m);
+      }
+      if (l == block_last(tw, k))
+        for (int sp = 0; sp < 2; ++sp) {
+          int m = c->ne[sp];
+          if (m == 0) continue;
+          double *Q = malloc(sizeof(double) * (size_t)N * m), *R = malloc(sizeof(double) * m * m);
+          for (int a = 0; a < nw; ++a) {
+            if (c->logw[a] == -INFINITY) continue;
+            double *ph = c->Phi[sp] + (size_t)a * N * m;
+            qr_pos(ph, N, m, Q, R);
+            memcpy(ph, Q, sizeof(double) * (size_t)N * m);
+          }
+          free(Q); free(R);
+        }
+      if (c->pc_every > 0 && l % c->pc_every == 0 && l < c->L) {
+        cp_comb(c, orc_uniform(c->seed, 0, ORC_S_CP_COMB, tag, (uint32_t)(l - 1), 0));
+        /* the copies' inverses are copied with them; mid-block they stay valid */
+      }
+    }
+  }
+  double mx = -INFINITY;
+  for (int a = 0; a < nw; ++a) if (c->logw[a] > mx) mx = c->logw[a];
+  if (mx == -INFINITY) {
+    *log_r = -INFINITY;
+  } else {
+    double W = 0.0;
+    for (int a = 0; a < nw; ++a) W += exp(c->logw[a] - mx);
+    *log_r = c->log_pc + mx + log(W / (double)nw);
+  }
+  free(u); free(v);
+  for (int sp = 0; sp < 2; ++sp) { free(LS[sp]); free(X[sp]); }
+  return 0;
+}
+
+int orc_cp_walker(const orc_cp *c, int32_t a, double *log_w, double *log_q, int8_t *fields) {
+  if (!c || a < 0 || a >= c->nw) { set_err("bad walker index"); return -1; }
+  if (log_w) *log_w = c->logw[a];
+  if (log_q) *log_q = c->logq[a];
+  if (fields) memcpy(fields, c->s + (size_t)a * c->L * c->N, (size_t)c->L * c->N);
+  return 0;
+}
+
+int orc_cp_stats(const orc_cp *c, double *log_pc, int64_t *cuts, int32_t *alive) {
+  if (!c) { set_err("null argument"); return -1; }
+  if (log_pc) *log_pc = c->log_pc;
+  if (cuts) *cuts = c->cuts;
+  if (alive) {
+    int n = 0;
+    for (int a = 0; a < c->nw; ++a) n += c->logw[a] > -INFINITY;
+    *alive = n;
+  }
+  return 0;
+}

@@ -47,7 +47,7 @@ enum { ORC_NO_FOCK = 1, ORC_NO_FLIPS = 2 };
 
 /* RNG streams of the counter-based generator */
 enum { ORC_S_FLIP = 1, ORC_S_SWAP_K = 2, ORC_S_SWAP_J = 3, ORC_S_SWAP_ACC = 4,
-       ORC_S_INIT_FIELD = 5, ORC_S_INIT_OCC = 6 };
+       ORC_S_INIT_FIELD = 5, ORC_S_INIT_OCC = 6, ORC_S_CP_FIELD = 7, ORC_S_CP_COMB = 8 };
 
 typedef struct orc_walker orc_walker;
 
@@ -98,6 +98,26 @@ int64_t orc_obs_size(const orc_walker *w);
 int orc_measure(const orc_walker *w, double *out);
 int orc_reset_measure(orc_walker *w);
 int orc_get_stats(const orc_walker *w, orc_stats *st);
+
+/* ---- Constrained-path (phaseless) inner walk, SM Sec. VI ----------------
+ * For one Fock state eta (occ_up, occ_dn), a population of n_walkers random
+ * walkers propagates Phi = P_eta through B_l(s) = E_K D0 F_l(s) with the
+ * Ising fields drawn site by site; each walker's weight is the product of
+ * the overlap ratios with the backward trial state <eta| e^{-(beta-tau) H_0}
+ * under the phaseless cut max(0, r).  log_r = log of the estimate of
+ *   R(eta) = E_{s uniform}[ prod_sigma det(P^T B^sigma(s) P) ] / W_T(eta).
+ * Field draws: orc_uniform(seed, walker slot, ORC_S_CP_FIELD, tag, l - 1, i);
+ * comb draw after slice l: orc_uniform(seed, 0, ORC_S_CP_COMB, tag, l - 1, 0). */
+enum { ORC_CP_IMPORTANCE = 0, ORC_CP_FREE = 1 };
+typedef struct orc_cp orc_cp;
+orc_cp *orc_cp_create(const orc_lattice *lat, const orc_params *par, const int32_t *occ_up,
+                      const int32_t *occ_dn, int32_t n_walkers, int32_t mode, int32_t pc_every);
+void orc_cp_destroy(orc_cp *c);
+int orc_cp_run(orc_cp *c, uint32_t tag, double *log_r);
+/* final log weight, sum of log p(s) of its draws (importance mode), and its
+ * field path [L][N] of walker slot a after the last run */
+int orc_cp_walker(const orc_cp *c, int32_t a, double *log_w, double *log_q, int8_t *fields);
+int orc_cp_stats(const orc_cp *c, double *log_pc, int64_t *cuts, int32_t *alive);
 
 #ifdef __cplusplus
 }
