@@ -14,6 +14,11 @@ Also measured, as objects of the same JSON line:
   320 slices), 64 walkers, FP64 and mixed precision (FP32 propagation);
 - flat_band: the 256-cell flat-band chain (N = 512, 128 + 128, beta = 10),
   128 walkers;
+- scaling_fig1: seconds per sweep against N on the paper's Fig. 1 workload
+  (square Hubbard, beta = 1, 50 + 50 particles, N = 144..16384) and the
+  fitted power of N;
+- constrained_path: the constrained-path inner walk (256 random walkers) of
+  one Fock state of the dilute gas;
 - serving: a Poisson stream of simulation requests (50/s, L x L from 16 to
   128, Ne per spin 4..64, U 2..8, beta 4..32, 100..1000 sweeps each)
   admitted by device footprint over a fixed window;
@@ -168,6 +173,8 @@ def main():
     ap.add_argument("--no-flat", action="store_true", help="skip the 128-walker flat-band batch")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cp", action="store_true", help="skip the constrained-path walk")
+    ap.add_argument("--no-scaling", action="store_true", help="skip the sweep-time-vs-N fit")
     ap.add_argument("--serve-window", type=float, default=60.0, help="seconds of the serving stream")
     ap.add_argument("--cpu-procs", type=int, default=0)
     args = ap.parse_args()
@@ -358,6 +365,56 @@ def run_legs(args, cfg, out):
         for w in fw:
             w.close()
         fctx.close()
+
+    if not args.no_scaling:
+        # sweep time against N on the paper's Fig. 1 workload (square Hubbard,
+        # dtau = 0.1, U = 2, T = 1: beta = 1, 10 slices; Ne = 100 as 50 + 50),
+        # one walker per lattice size, and the fitted power of N
+        pts = []
+        for Ls in (12, 16, 24, 32, 48, 64, 96, 128):
+            lat = W.square_lattice(Ls)
+            par = W.Params(U=2.0, beta=1.0, dtau=0.1, n_stab=10, n_up=50, n_dn=50, seed=Ls, walker_id=0)
+            note(f"scaling: {Ls}x{Ls}")
+            wk = lecqmc.Walker(ctx, lat, par)
+            wk.sweep(1)
+            ctx.synchronize()
+            t1 = time.perf_counter()
+            wk.sweep(3)
+            ctx.synchronize()
+            pts.append((lat.n_sites, (time.perf_counter() - t1) / 3))
+            wk.close()
+        Ns = np.array([p[0] for p in pts], float)
+        ts = np.array([p[1] for p in pts])
+        slope_all = float(np.polyfit(np.log(Ns), np.log(ts), 1)[0])
+        big = Ns >= 1024
+        slope_big = float(np.polyfit(np.log(Ns[big]), np.log(ts[big]), 1)[0])
+        out["scaling_fig1"] = {
+            "sec_per_sweep_by_N": {str(int(n)): t for n, t in pts},
+            "fitted_power_of_N": slope_all, "fitted_power_of_N_N_ge_1024": slope_big,
+            "config": "L x L periodic square Hubbard, dtau=0.1, U=2, T=1 (beta=1, 10 slices), 50+50 particles, "
+                      "one walker, FP64, default chain shape; seconds per full sweep (flips, QR, Fock swaps)"}
+
+    if not args.no_cp:
+        # constrained-path inner walk: one Fock state of the dilute gas, 256
+        # random walkers, importance sampling, a comb every 40 slices
+        lat, par = W.config_dilute(seed=1)
+        ou, od = W.random_occupation(1024, 8, 21), W.random_occupation(1024, 8, 22)
+        nw = 256
+        note(f"constrained path: {nw} walkers on the dilute gas")
+        cp = lecqmc.CPWalk(ctx, lat, par, ou, od, nw, lecqmc.CP_IMPORTANCE, 40)
+        cp.run(0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lr = cp.run(1)
+        wl = time.perf_counter() - t1
+        st = cp.stats()
+        cp.close()
+        out["constrained_path"] = {
+            "value": nw * lat.n_sites * par.L_tau / wl, "unit": "HS-field draws/s", "walkers": nw,
+            "ms_per_walk": wl * 1e3, "log_R_estimate": lr, "cuts": st["cuts"],
+            "config": "32x32 periodic Hubbard, U=4, one Fock state of 8+8 particles, beta=16, dtau=0.05 "
+                      "(320 slices), QR every 10 slices, 256 walkers, importance sampling, comb every 40 "
+                      "slices, FP64"}
 
     if not args.no_serving:
         from paper_2601_08552_amd import serve

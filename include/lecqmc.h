@@ -266,6 +266,56 @@ int lecqmc_swap_ratio(lecqmc_walker *w, int32_t spin, int32_t k_index, int32_t j
 
 const char *lecqmc_last_error(void);
 
+/* ---- Constrained-path (phaseless) inner walk (SM Sec. VI) ----------------
+ * Two-stage sampling of the canonical partition function: Fock states eta are
+ * drawn with the trial weight W_T(eta) = <eta| e^{-beta H_0} |eta> (the chain
+ * of a walker with U = 0), and for one eta a population of random walkers
+ * estimates
+ *   R(eta) = E_s[ prod_sigma det(P^T B^sigma(s) P) ] / W_T(eta)
+ * (s uniform over the Ising fields) as the product of the overlap ratios of
+ * each walker with the backward trial state <eta| e^{-(beta - tau_l) H_0}, the
+ * fields drawn site by site with rank-1 (Sherman-Morrison) updates and the
+ * phaseless cut max(0, r).  H_0 is the lattice's one-body part (hopping and
+ * onsite energies); the interaction is the Ising decoupling of U with the
+ * walker parameters' U, beta, dtau and n_stab (QR of each walker every n_stab
+ * slices).
+ * Field draws of walker slot a at slice l, site i: the counter-based uniform
+ * of (seed, walker_id = a, stream 7, sweep = tag, l - 1, i); the comb after
+ * slice l: (seed, 0, stream 8, tag, l - 1, 0).
+ *   mode LECQMC_CP_IMPORTANCE: s = +1 with probability
+ *     max(0, r(+1)) / (max(0, r(+1)) + max(0, r(-1))), the weight times
+ *     (max(0, r(+1)) + max(0, r(-1))) / 2;
+ *   mode LECQMC_CP_FREE: s = +1 with probability 1/2, the weight times
+ *     max(0, r(s)).
+ * A walker whose factor is 0 is dead (weight 0) and draws nothing more.
+ * pc_every > 0: after every pc_every-th slice (not the last) a comb with one
+ * uniform draw replaces the population by n_walkers copies chosen in
+ * proportion to their weights, each of weight 1; the log of the mean weight
+ * is accumulated into the estimate.
+ * Limits: FP64 only; n_up, n_dn <= 64 (the inverses live in LDS). */
+#define LECQMC_CP_IMPORTANCE 0
+#define LECQMC_CP_FREE 1
+typedef struct lecqmc_cp lecqmc_cp;
+/* The Fock state (occ_up[n_up], occ_dn[n_dn], distinct sites) and the
+ * population size; builds the U = 0 trial walker and its backward trial
+ * states (device memory counted against the context budget).  EINVAL on bad
+ * arguments or limits, ENOMEM over the budget. */
+int lecqmc_cp_create(lecqmc_ctx *ctx, const lecqmc_lattice *lat, const lecqmc_params *par,
+                     const int32_t *occ_up, const int32_t *occ_dn, int32_t n_walkers, int32_t mode,
+                     int32_t pc_every, lecqmc_cp **out);
+/* One inner walk from Phi = P_eta over all slices; *log_r = log of the
+ * estimate of R(eta) (-inf when every walker died).  Blocks until done. */
+int lecqmc_cp_run(lecqmc_cp *cp, uint32_t tag, double *log_r);
+/* After a run: walker slot a's log weight (since the last comb), the sum of
+ * the log probabilities of its draws (importance mode; copied with it by a
+ * comb) and its field path (host int8[L_tau][n_sites], 0 where it drew
+ * nothing); any pointer may be NULL. */
+int lecqmc_cp_walker(lecqmc_cp *cp, int32_t a, double *log_w, double *log_q, int8_t *fields);
+/* After a run: accumulated log mean weight of the combs, walkers cut by the
+ * constraint, walkers alive at the end. */
+int lecqmc_cp_stats(lecqmc_cp *cp, double *log_pc, int64_t *cuts, int32_t *alive);
+int lecqmc_cp_destroy(lecqmc_cp *cp);
+
 #ifdef __cplusplus
 }
 #endif

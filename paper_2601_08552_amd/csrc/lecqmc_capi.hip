@@ -1213,3 +1213,184 @@ extern "C" int lecqmc_swap_ratio(lecqmc_walker *w, int32_t spin, int32_t k, int3
   HIPCHK(xfer(w->ctx, ratio, w->h.dbg, sizeof(double), hipMemcpyDeviceToHost));
   return check_status(w);
 }
+
+// ---------------------------------------------------------------------------
+// Constrained-path inner walk (SM Sec. VI): a population of random walkers of
+// one Fock state, guided by the U = 0 trial walker of the same state.
+// ---------------------------------------------------------------------------
+struct lecqmc_cp {
+  lecqmc_ctx *ctx;
+  lecqmc_walker *trial;   // U = 0, the Fock state eta: tables and the backward trial states
+  CpDesc d;               // d.cur = the live walker states
+  CpState other;          // the comb's destination
+  void *dmem;
+  size_t bytes;
+  int N, L, nw, pc_every;
+  LdsPlan plan;
+};
+
+extern "C" int lecqmc_cp_create(lecqmc_ctx *ctx, const lecqmc_lattice *lat, const lecqmc_params *par,
+                                const int32_t *occ_up, const int32_t *occ_dn, int32_t n_walkers, int32_t mode,
+                                int32_t pc_every, lecqmc_cp **out) {
+  if (!ctx || !out || !par || !occ_up || !occ_dn) return fail(LECQMC_EINVAL, "null argument");
+  if (n_walkers < 1 || (mode != LECQMC_CP_IMPORTANCE && mode != LECQMC_CP_FREE) || pc_every < 0)
+    return fail(LECQMC_EINVAL, "bad walker count, mode or control interval");
+  if (par->precision != LECQMC_FP64) return fail(LECQMC_EINVAL, "the constrained-path walk runs in FP64 only");
+  if (par->n_up > kLdsNe || par->n_dn > kLdsNe)
+    return fail(LECQMC_EINVAL, "the constrained-path walk holds its inverses in LDS: Ne <= %d per spin", kLdsNe);
+  lecqmc_params p0 = *par;
+  p0.U = 0.0;
+  p0.flags = LECQMC_NO_FLIPS | LECQMC_NO_FOCK;
+  lecqmc_walker *tw = nullptr;
+  if (int rc = lecqmc_create_walker(ctx, lat, &p0, nullptr, occ_up, occ_dn, &tw)) return rc;
+  const int N = tw->N, L = tw->L, ne0 = tw->ne[0], ne1 = tw->ne[1];
+  const int mm = std::max(std::max(ne0, ne1), 1);
+  const size_t nw = (size_t)n_walkers;
+  // per walker: two state sets (phi, inverse, field path, weights), QR scratch
+  const size_t phi_b = (size_t)N * (ne0 + ne1) * sizeof(double);
+  const size_t inv_b = (size_t)(ne0 * ne0 + ne1 * ne1) * sizeof(double);
+  const size_t per = 2 * (align256(phi_b) + align256(inv_b) + align256((size_t)L * N) + 2 * sizeof(double)) +
+                     align256(phi_b) + 2 * (size_t)mm * mm * sizeof(double) + sizeof(long long) + sizeof(int);
+  const size_t total = nw * per + 4096;
+  if (ctx->budget && ctx->used + total > ctx->budget) {
+    lecqmc_destroy_walker(tw);
+    return fail(LECQMC_ENOMEM, "constrained-path population needs %zu bytes, %zu of %zu in use", total, ctx->used,
+                ctx->budget);
+  }
+  void *dmem = nullptr;
+  hipError_t e = hipMalloc(&dmem, total);
+  if (e != hipSuccess) {
+    lecqmc_destroy_walker(tw);
+    return fail(LECQMC_EDEVICE, "hipMalloc: %s", hipGetErrorString(e));
+  }
+  char *b = (char *)dmem;
+  auto take = [&](size_t n) { char *r = b; b += align256(n); return r; };
+  lecqmc_cp *c = new lecqmc_cp();
+  c->ctx = ctx;
+  c->trial = tw;
+  c->dmem = dmem;
+  c->bytes = total;
+  c->N = N;
+  c->L = L;
+  c->nw = n_walkers;
+  c->pc_every = pc_every;
+  CpState *sets[2] = {&c->d.cur, &c->other};
+  for (CpState *st : sets) {
+    st->phi[0] = (double *)take(nw * N * ne0 * sizeof(double));
+    st->phi[1] = (double *)take(nw * N * ne1 * sizeof(double));
+    st->minv[0] = (double *)take(nw * ne0 * ne0 * sizeof(double));
+    st->minv[1] = (double *)take(nw * ne1 * ne1 * sizeof(double));
+    st->s = (int8_t *)take(nw * L * N);
+    st->logw = (double *)take(nw * sizeof(double));
+    st->logq = (double *)take(nw * sizeof(double));
+  }
+  c->d.tmp[0] = (double *)take(nw * N * ne0 * sizeof(double));
+  c->d.tmp[1] = (double *)take(nw * N * ne1 * sizeof(double));
+  c->d.vacc = (double *)take(nw * 2 * mm * mm * sizeof(double));
+  c->d.cuts = (long long *)take(nw * sizeof(long long));
+  c->d.pick = (int *)take(nw * sizeof(int));
+  c->d.log_pc = (double *)take(sizeof(double));
+  c->d.nw = n_walkers;
+  c->d.mode = mode;
+  c->d.mm = mm;
+  c->d.seed = par->seed;
+  const double lam = acosh(exp(par->dtau * par->U / 2.0));
+  for (int sp = 0; sp < 2; ++sp)
+    for (int u = 0; u < 2; ++u) {
+      const double sigma = sp == 0 ? 1.0 : -1.0, s = u == 0 ? 1.0 : -1.0;
+      c->d.delta[sp][u] = exp(sigma * lam * s) - 1.0;
+    }
+  ctx->used += total;
+  const LaunchCfg cf = launch_cfg(&tw, 1);
+  c->plan = LdsPlan{mm, 0, 0, cf.left.bond_words, 0, 0, 0, 0};
+  if (lds_bytes(c->plan) > kLdsLimit) c->plan.bond_words = 0;   // bonds then read from device memory
+  // the backward trial states X_l at every slice: the trial walker's left stack
+  e = launch_left_stack(tw->d_desc, 1, cf.left, 0, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    lecqmc_cp_destroy(c);
+    return fail(LECQMC_EDEVICE, "trial left stack: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return 0;
+}
+
+extern "C" int lecqmc_cp_run(lecqmc_cp *c, uint32_t tag, double *log_r) {
+  if (!c || !log_r) return fail(LECQMC_EINVAL, "null argument");
+  lecqmc_ctx *ctx = c->ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  HIPCHK(launch_cp_init(c->trial->d_desc, c->d, st));
+  HIPCHK(hipMemsetAsync(c->d.log_pc, 0, sizeof(double), st));
+  for (int l = 1; l <= c->L;) {
+    int le = c->L;
+    if (c->pc_every > 0) le = std::min(c->L, ((l - 1) / c->pc_every + 1) * c->pc_every);
+    HIPCHK(timed(ctx, 1, [&] { return launch_cp_walk(c->trial->d_desc, c->d, c->plan, l, le, tag, st); }));
+    if (c->pc_every > 0 && le % c->pc_every == 0 && le < c->L) {
+      HIPCHK(launch_cp_comb(c->d, c->other, c->trial->d_desc, le, tag, st));
+      std::swap(c->d.cur, c->other);
+    }
+    l = le + 1;
+  }
+  std::vector<double> lw(c->nw);
+  double lpc = 0.0;
+  HIPCHK(hipMemcpyAsync(lw.data(), c->d.cur.logw, sizeof(double) * c->nw, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&lpc, c->d.log_pc, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double mx = -INFINITY;
+  for (double v : lw) mx = std::max(mx, v);
+  if (mx == -INFINITY) {
+    *log_r = -INFINITY;
+  } else {
+    double W = 0.0;
+    for (double v : lw) W += exp(v - mx);
+    *log_r = lpc + mx + log(W / (double)c->nw);
+  }
+  return 0;
+}
+
+extern "C" int lecqmc_cp_walker(lecqmc_cp *c, int32_t a, double *log_w, double *log_q, int8_t *fields) {
+  if (!c || a < 0 || a >= c->nw) return fail(LECQMC_EINVAL, "bad walker index");
+  lecqmc_ctx *ctx = c->ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  if (log_w) HIPCHK(xfer(ctx, log_w, c->d.cur.logw + a, sizeof(double), hipMemcpyDeviceToHost));
+  if (log_q) HIPCHK(xfer(ctx, log_q, c->d.cur.logq + a, sizeof(double), hipMemcpyDeviceToHost));
+  if (fields)
+    HIPCHK(xfer(ctx, fields, c->d.cur.s + (size_t)a * c->L * c->N, (size_t)c->L * c->N, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+extern "C" int lecqmc_cp_stats(lecqmc_cp *c, double *log_pc, int64_t *cuts, int32_t *alive) {
+  if (!c) return fail(LECQMC_EINVAL, "null argument");
+  lecqmc_ctx *ctx = c->ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  std::vector<double> lw(c->nw);
+  std::vector<long long> cu(c->nw);
+  double lpc = 0.0;
+  HIPCHK(xfer(ctx, lw.data(), c->d.cur.logw, sizeof(double) * c->nw, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(ctx, cu.data(), c->d.cuts, sizeof(long long) * c->nw, hipMemcpyDeviceToHost));
+  HIPCHK(xfer(ctx, &lpc, c->d.log_pc, sizeof(double), hipMemcpyDeviceToHost));
+  if (log_pc) *log_pc = lpc;
+  if (cuts) {
+    long long s = 0;
+    for (long long v : cu) s += v;
+    *cuts = s;
+  }
+  if (alive) {
+    int n = 0;
+    for (double v : lw) n += v > -INFINITY;
+    *alive = n;
+  }
+  return 0;
+}
+
+extern "C" int lecqmc_cp_destroy(lecqmc_cp *c) {
+  if (!c) return 0;
+  (void)hipSetDevice(c->ctx->device);
+  (void)hipStreamSynchronize(c->ctx->stream);
+  (void)hipFree(c->dmem);
+  c->ctx->used -= c->bytes;
+  lecqmc_destroy_walker(c->trial);
+  delete c;
+  return 0;
+}

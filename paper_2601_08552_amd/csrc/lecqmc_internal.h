@@ -25,7 +25,8 @@ __host__ __device__ inline int mfma_lds_doubles(int ne0, int ne1) {
 }
 
 // counter-based generator streams (shared layout with the walker's key)
-enum Stream : uint32_t { kFlip = 1, kSwapK = 2, kSwapJ = 3, kSwapAcc = 4, kInitField = 5, kInitOcc = 6 };
+enum Stream : uint32_t { kFlip = 1, kSwapK = 2, kSwapJ = 3, kSwapAcc = 4, kInitField = 5, kInitOcc = 6,
+                         kCpField = 7, kCpComb = 8 };
 
 // Scalars of one walker that kernels update (device memory).
 struct Scalars {
@@ -144,5 +145,32 @@ hipError_t launch_measure(const WalkerDesc *d_descs, int n, int slots, LdsPlan p
 hipError_t launch_green(const WalkerDesc *d_desc, int max_ne, int boundary, int spin, double *G, hipStream_t st);
 hipError_t launch_flip_ratio(const WalkerDesc *d_desc, int max_ne, int slice, int site, hipStream_t st);
 hipError_t launch_swap_ratio(const WalkerDesc *d_desc, int max_ne, int spin, int k, int j, hipStream_t st);
+
+// Constrained-path population of one Fock state (device arrays, one set of
+// walker states; the comb copies into a second set).  The trial walker (U = 0,
+// the same Fock state) supplies the tables and, from its left stack, the
+// backward trial states at every slice.
+struct CpState {
+  double *phi[2];       // [nw][N][ne]   walker Slater blocks
+  double *minv[2];      // [nw][ne][ne]  (X^T Phi)^{-1} at a segment end
+  int8_t *s;            // [nw][L][N]    drawn field path
+  double *logw, *logq;  // [nw]
+};
+struct CpDesc {
+  CpState cur;
+  double *tmp[2];       // [nw][N][ne]   QR scratch
+  double *vacc;         // [nw][2][mm][mm] QR scratch
+  long long *cuts;      // [nw]
+  int *pick;            // [nw] comb sources
+  double *log_pc;       // [1] sum of log(mean weight) over the combs
+  int nw, mode, mm;
+  uint64_t seed;
+  double delta[2][2];   // [spin][s = +1, -1]: exp(sigma lambda s) - 1
+};
+hipError_t launch_cp_init(const WalkerDesc *trial, CpDesc cp, hipStream_t st);
+hipError_t launch_cp_walk(const WalkerDesc *trial, CpDesc cp, LdsPlan p, int l_begin, int l_end, uint32_t tag,
+                          hipStream_t st);
+// comb after slice l: sources from cp.cur's weights, states copied into dst
+hipError_t launch_cp_comb(CpDesc cp, CpState dst, const WalkerDesc *trial, int l, uint32_t tag, hipStream_t st);
 
 }  // namespace lecqmc

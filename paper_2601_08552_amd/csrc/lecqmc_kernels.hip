@@ -212,6 +212,14 @@ __device__ __forceinline__ lds_i8 *as_lds(int8_t *p) { return (lds_i8 *)p; }
 typedef __attribute__((address_space(3))) int lds_i32;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 
+// One v_mfma_f64_16x16x4f64 (FP64 matrix cores).  Operand layouts (lane l,
+// c = l % 16, g = l / 16): A (16 x 4) holds A[c][g], B (4 x 16) holds
+// B[g][c], and element j of the 16 x 16 result holds D[4 j + g][c].
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // bond (i, j, cosh, -sinh) of bond b: from the compact LDS tables when they
 // were loaded, from device memory otherwise
 struct BondSrc {
@@ -450,10 +458,85 @@ __device__ __forceinline__ double gram_rows(PX X, int mx, int pa, PY Y, int my, 
   return (a0 + a1) + (a2 + a3);
 }
 
+// out = X^T Y on the FP64 matrix cores, for Gram matrices larger than one
+// entry per thread: 16 x 16 output tiles, four rows per step (A = X^T and
+// B = Y: lane (c, g) loads X[i + g][p0 + c] and Y[i + g][q0 + c]; columns and
+// rows past the ends load a clamped address and contribute zero).  A wave
+// owns groups of up to four tiles that share one p tile (one A load per
+// step).  With fewer groups than waves the rows are split among the waves
+// and the partial tiles are added into out in a fixed wave order, so the
+// result does not depend on timing.
+template <typename PX, typename PY>
+__device__ void gram_mfma(PX X, int mx, PY Y, int my, int N, double *out) {
+  const int tp = (mx + 15) >> 4, tq = (my + 15) >> 4;
+  const int qg = tq < 4 ? tq : 4;            // tiles per group
+  const int gq = (tq + qg - 1) / qg;         // groups per p tile
+  const int ng = tp * gq;
+  const int ks = ng >= 4 ? 1 : 4 / ng;       // row splits (ng * ks <= 4 when ks > 1)
+  const int wave = TID >> 6, lane = TID & 63, c = lane & 15, g = lane >> 4;
+  const int steps = (N + 3) >> 2;
+  for (int it = wave; it < ng * ks; it += 4) {
+    const int grp = it % ng, part = it / ng;
+    const int pt = grp / gq, qt0 = (grp - pt * gq) * qg;
+    const int nq = min(qg, tq - qt0);
+    const int s0 = (int)((long)steps * part / ks), s1 = (int)((long)steps * (part + 1) / ks);
+    const int pc = pt * 16 + c;
+    const bool pv = pc < mx;
+    const int pcc = pv ? pc : mx - 1;
+    int qcc[4];
+    bool qv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = (qt0 + j) * 16 + c;
+      qv[j] = j < nq && q < my;
+      qcc[j] = qv[j] ? q : my - 1;
+    }
+    v4d acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int st = s0; st < s1; ++st) {
+      const int i = 4 * st + g;
+      const bool iv = i < N;
+      const int ic = iv ? i : N - 1;
+      const double xa = (double)X[(size_t)ic * mx + pcc];
+      double yb[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yb[j] = (double)Y[(size_t)ic * my + qcc[j]];
+      const double a = (iv && pv) ? xa : 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < nq) acc[j] = mfma_f64(a, (iv && qv[j]) ? yb[j] : 0.0, acc[j]);
+    }
+    // ks == 1: every tile is computed by one wave; ks > 1 only when
+    // ng * ks == 4 (one item per wave, so every wave meets the same
+    // barriers): the wave holding row part `part` adds its tiles in phase part
+    for (int ph = 0; ph < ks; ++ph) {
+      if (ph == part) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nq && qv[j])
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int p = pt * 16 + 4 * r + g;
+              if (p < mx) {
+                double &o = out[p * my + (qt0 + j) * 16 + c];
+                o = ph == 0 ? acc[j][r] : o + acc[j][r];
+              }
+            }
+      }
+      if (ks > 1) SYNC();
+    }
+  }
+  SYNC();
+}
+
 template <typename PX, typename PY>
 __device__ void gram_t(PX X, int mx, PY Y, int my, int N, double *out, double *red, const int *sub, int sa) {
   const int P = mx * my;
-  if (P <= kThreads) {
+  if (P > kThreads && !sub) {
+    gram_mfma(X, mx, Y, my, N, out);
+  } else if (P <= kThreads) {
     const int G = kThreads / P;
     const int g = TID / P, p = TID - g * P;
     double acc = 0.0;
@@ -529,9 +612,64 @@ __device__ void tri_inverse(const double *R, int m, double *Ri) {
   SYNC();
 }
 
+// out = in * Ri (Ri upper triangular, m x m) on the FP64 matrix cores,
+// m > 8: one 16-row strip per wave at a time, output tiles of 16 columns
+// from the last to the first.  Tile t (columns 16 t .. 16 t + 15) reads only
+// the strip's columns below 16 t + 16 (Ri[k][q] = 0 for k > q) and those have
+// not been stored yet, so in and out may be the same block (lane (c, g)
+// loads in[i0 + c][4 k + g] as the A operand).  The result also goes to out2
+// (if set).
+template <typename PI, typename PO>
+__device__ void trimul_mfma(PI in, PO out, double *out2, int N, int m, const double *Ri) {
+  const int wave = TID >> 6, lane = TID & 63, c = lane & 15, g = lane >> 4;
+  const int nks = (m + 3) >> 2, tq = (m + 15) >> 4;
+  const double *R = Ri;   // LDS, or device memory when the launch keeps its Ne x Ne matrices there
+  for (int st = wave; st * 16 < N; st += 4) {
+    const int i = st * 16 + c;
+    const bool iv = i < N;
+    const int ic = iv ? i : N - 1;
+    for (int t = tq - 1; t >= 0; --t) {
+      const int q = t * 16 + c;
+      const bool qv = q < m;
+      const int qc = qv ? q : m - 1;
+      const int kend = min(nks, 4 * t + 4);
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+      for (int k = 0; k < kend; ++k) {
+        const int kk = 4 * k + g;
+        const bool kv = kk < m;
+        const int kc = kv ? kk : m - 1;
+        const double a = (double)in[(size_t)ic * m + kc];
+        const double b = R[kc * m + qc];
+        acc = mfma_f64((iv && kv) ? a : 0.0, (kv && qv) ? b : 0.0, acc);
+      }
+      if (qv)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = st * 16 + 4 * r + g;
+          if (row < N) {
+            out[(size_t)row * m + q] = acc[r];
+            if (out2) out2[(size_t)row * m + q] = acc[r];
+          }
+        }
+    }
+  }
+}
+
 // out = in * Ri (Ri upper triangular), written to out and out2 (if set)
 template <typename TI>
 __device__ void right_tri_mul(const TI *in, double *out, double *out2, int N, int m, const double *Ri) {
+  if (m > 8) {
+    if (in_lds(in)) {
+      if (in_lds(out)) trimul_mfma(as_lds(in), as_lds(out), out2, N, m, Ri);
+      else trimul_mfma(as_lds(in), out, out2, N, m, Ri);
+    } else {
+      if (in_lds(out)) trimul_mfma(in, as_lds(out), out2, N, m, Ri);
+      else trimul_mfma(in, out, out2, N, m, Ri);
+    }
+    SYNC();
+    return;
+  }
   const int tot = N * m;
   for (int t = TID; t < tot; t += kThreads) {
     const int i = t / m, c = t - (t / m) * m;
@@ -582,6 +720,12 @@ __device__ __forceinline__ void tri_mul_rows_t(P X, double *out2, int N, int m, 
 }
 template <int MR>
 __device__ __forceinline__ void tri_mul_rows(double *X, double *out2, int N, int m, const double *Ri) {
+  if (m > MR) {
+    if (in_lds(X)) trimul_mfma(as_lds(X), as_lds(X), out2, N, m, Ri);
+    else trimul_mfma(X, X, out2, N, m, Ri);
+    SYNC();
+    return;
+  }
   if (in_lds(X)) tri_mul_rows_t<MR>(as_lds(X), out2, N, m, Ri);
   else tri_mul_rows_t<MR>(X, out2, N, m, Ri);
 }
@@ -1315,10 +1459,6 @@ __device__ __forceinline__ void delayed_epilogue(const WalkerDesc &w, Lds &L, do
 // A (16 x 4) holds A[c][g], B (4 x 16) holds B[g][c], and element j of the
 // 16 x 16 result holds D[4 j + g][c].
 // ---------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // The chain's chunk matrices.  U (Ne16 x 17 per spin, for the update) in LDS
 // or, when the launch has no room, in the walker's device scratch; the two
@@ -1612,9 +1752,9 @@ typedef __attribute__((address_space(1))) const float gc_f32;
 typedef __attribute__((address_space(1))) const double gc_f64;
 __device__ __forceinline__ gc_f64 *as_global(const double *p) { return (gc_f64 *)p; }
 __device__ __forceinline__ gc_f32 *as_global(const float *p) { return (gc_f32 *)p; }
-template <typename F>
-__device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, int i0, int bufi,
-                            F *const phi[2], bool resident, int mm, int t0, int nt) {
+template <typename F, bool fdiag>
+__device__ void stage_chunk_t(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, int i0, int bufi,
+                              F *const phi[2], bool resident, int mm, int t0, int nt) {
   if (TID < t0 || TID >= t0 + nt) return;
   const int S = L.S, N = w.N;
   const int cnt = min(S, N - i0);
@@ -1639,6 +1779,11 @@ __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, 
   bool first = true;
   for (int e0 = tid; e0 < tot || first; e0 += 8 * nt) {
     double xv[2][8], pv[2][8];
+    // D_l of this slice for the streamed right rows (fdiag): the field and
+    // onsite factor of each element's row, loaded with the rows and applied
+    // at the store, in the storage precision (the product diag_t forms)
+    int sr[8];
+    double er[8];
     const int r0 = r, a0 = a;
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
@@ -1650,6 +1795,13 @@ __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, 
         const bool ok = e0 + u * nt < tot && a < m;
         xv[sp][u] = ok ? (double)lx[sp][r * m + a] : 0.0;
         pv[sp][u] = (ok && !resident) ? (double)pr[sp][r * m + a] : 0.0;
+        if constexpr (fdiag) {
+          if (sp == 0) {
+          const int rc = r < cnt ? r : cnt - 1;
+          sr[u] = srow[i0 + rc];
+          er[u] = w.eps_fac[i0 + rc];
+          }
+        }
         a += da;
         r += dr;
         if (a >= mm) { a -= mm; ++r; }
@@ -1673,7 +1825,15 @@ __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, 
         const int e = e0 + u * nt;
         if (e < tot) {
           xd[sp][e] = xv[sp][u];
-          if (!resident) pd[sp][e] = pv[sp][u];
+          if (!resident) {
+            if constexpr (fdiag) {
+              const int ss = sp == 0 ? sr[u] : -sr[u];
+              const F f = (F)((ss > 0 ? w.elam : w.emlam) * er[u]);
+              pd[sp][e] = (double)((F)pv[sp][u] * f);
+            } else {
+              pd[sp][e] = pv[sp][u];
+            }
+          }
         }
       }
   }
@@ -1685,6 +1845,21 @@ __device__ void stage_chunk(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, 
     L.dl[(bufi * 2 + 0) * S + rr] = v > 0 ? w.delta_dn_s : w.delta_up_s;
     L.dl[(bufi * 2 + 1) * S + rr] = -v > 0 ? w.delta_dn_s : w.delta_up_s;
   }
+}
+
+// fdiag is a template argument, and only the chains that may fuse D_l
+// (FUSE) carry the fused variant, so that the others keep the staging code
+// they had without it
+template <bool FUSE, typename F>
+__device__ __forceinline__ void stage_d(const WalkerDesc &w, Lds &L, int l, uint32_t sweep, int i0, int bufi,
+                                        F *const phi[2], bool resident, int mm, int t0, int nt, bool fdiag) {
+  if constexpr (FUSE) {
+    if (fdiag) {
+      stage_chunk_t<F, true>(w, L, l, sweep, i0, bufi, phi, resident, mm, t0, nt);
+      return;
+    }
+  }
+  stage_chunk_t<F, false>(w, L, l, sweep, i0, bufi, phi, resident, mm, t0, nt);
 }
 
 // Write back chunk rows after the chain: flip the accepted fields and scale
@@ -1745,6 +1920,9 @@ template <int T, typename F>
 __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2],
                               bool resident, int mm, ChainAcc &acc) {
   constexpr bool kReg = T > 0 && T != kDelayed && T != kMfma;   // register-tiled inverse
+  // chains that stage D_l with the streamed rows (T = 1 serves Ne <= 8, whose
+  // blocks nearly always stay resident, and keeps the staging it had)
+  constexpr bool kFuseD = T == 0 || T == 2 || T == 4;
   constexpr int TT = kReg ? T : 1;
   const int N = w.N, S = L.S;
   const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
@@ -1779,11 +1957,18 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
     }
   }
   for (int l = l0; l <= l1; ++l) {
-    if (l > l0)
+    // D_l: applied while a streamed block is staged for the site-by-site
+    // chains of kFuseD, whose staging runs beside a longer chain; by a pass
+    // for the delayed chains (their staging is the longer side of a chunk,
+    // and the fused factors measured slower there than the pass), for
+    // resident blocks, and before the block's first slice, where the fresh
+    // inverse needs it
+    const bool fd = kFuseD && l > l0 && !resident && !(w.flags & 2);
+    if (l > l0 && !fd)
       for (int s2 = 0; s2 < 2; ++s2) apply_diag(w, phi[s2], w.ne[s2], l, s2, false);
     if constexpr (T == kDelayed) {
       if (!(w.flags & 2)) {
-        stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
+        stage_d<kFuseD>(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads, fd);
         SYNC();
         for (int c = 0; c < nch; ++c) {
           const int bufi = c & 1, i0 = c * S;
@@ -1808,7 +1993,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
             if (TID == 0) L.iscal[8 + bufi] = (int)mask;
           } else {
             if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
-            if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+            if (c + 1 < nch) stage_d<kFuseD>(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64, fd);
           }
           SYNC();
           // c u~ goes to this chunk's staging half, free once its rows are consumed
@@ -1824,7 +2009,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
         const bool uw_lds = L.dgn >= mfma_lds_doubles(w.ne[0], w.ne[1]);
         const MfBufs mb = mfbufs(w, L.dg, uw_lds);
         const bool mlds = in_lds(L.Ms0);
-        stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
+        stage_d<kFuseD>(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads, fd);
         SYNC();
         for (int c = 0; c < nch; ++c) {
           const int bufi = c & 1, i0 = c * S;
@@ -1832,7 +2017,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
           const double *xsb = L.xs + (size_t)bufi * 2 * S * mm;
           auto side = [&]() {
             if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
-            if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+            if (c + 1 < nch) stage_d<kFuseD>(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64, fd);
           };
           // right rows from the resident block (storage F, row stride Ne) or
           // the FP64 staging buffer (row stride mm); U, W and the inverses
@@ -1857,7 +2042,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
         SYNC();
       }
     } else if (!(w.flags & 2)) {
-      stage_chunk(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads);
+      stage_d<kFuseD>(w, L, l, sweep, 0, 0, phi, resident, mm, 0, kThreads, fd);
       SYNC();
       for (int c = 0; c < nch; ++c) {
         const int bufi = c & 1, i0 = c * S;
@@ -1884,7 +2069,7 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
           if (TID == 0) L.iscal[8 + bufi] = (int)mask;
         } else {
           if (c >= 1) flush_chunk(w, L, l, (c - 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
-          if (c + 1 < nch) stage_chunk(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64);
+          if (c + 1 < nch) stage_d<kFuseD>(w, L, l, sweep, (c + 1) * S, bufi ^ 1, phi, resident, mm, 64, kThreads - 64, fd);
         }
         SYNC();
       }
@@ -2807,6 +2992,84 @@ __device__ __forceinline__ void fock_sub_t(const double *Qg, int ne, int N, PF f
   }
 }
 
+// One pass over Q for the second Gram-Schmidt pass: f[i] -= sum_a Q[i][a] z[a]
+// (as fock_sub), and y[a] = sum_i Q[i][a] f[i] of the updated f (as fock_qt),
+// from the same loaded rows.  Rows, lanes and summation order are those of
+// the two separate passes, so y and f come out bit-identical to them.  For
+// ne <= 128 (one column pair per lane).
+constexpr int kQF = 8;   // row groups in flight per lane in the fused pass (it holds four arrays)
+template <bool VEC, typename PF>
+__device__ __forceinline__ void fock_subqt_t(const double *Qg, int ne, int N, PF f, const double *z, double *y,
+                                             double *red) {
+  using FE = typename Elem<PF>::T;
+  gc_f64 *Q = as_global(Qg);
+  const lds_f64 *zl = as_lds(z);
+  const QMap mp = qmap(ne);
+  const int wave = TID >> 6, step = 4 * mp.rpi;
+  const int cc = 2 * mp.col;
+  const double zc0 = cc < ne ? zl[cc] : 0.0, zc1 = cc + 1 < ne ? zl[cc + 1] : 0.0;
+  double a0 = 0.0, a1 = 0.0;
+  for (int i0 = wave * mp.rpi; i0 < N; i0 += kQF * step) {
+    double x0[kQF], x1[kQF], fo[kQF], sm[kQF];
+#pragma unroll
+    for (int u = 0; u < kQF; ++u) qpair<VEC>(Q, ne, N, i0 + u * step + mp.rsub, mp.col, x0[u], x1[u]);
+#pragma unroll
+    for (int u = 0; u < kQF; ++u) fo[u] = (double)f[min(i0 + u * step + mp.rsub, N - 1)];
+    __builtin_amdgcn_sched_barrier(0);   // every load of the round goes out before the first use
+#pragma unroll
+    for (int u = 0; u < kQF; ++u) qzero(ne, N, i0 + u * step + mp.rsub, mp.col, x0[u], x1[u]);
+#pragma unroll
+    for (int u = 0; u < kQF; ++u) sm[u] = fma(x1[u], zc1, fma(x0[u], zc0, 0.0));
+    for (int m = 1; m < mp.ne2; m <<= 1)
+#pragma unroll
+      for (int u = 0; u < kQF; ++u) sm[u] += __shfl_xor(sm[u], m);
+#pragma unroll
+    for (int u = 0; u < kQF; ++u) {
+      const int ii = i0 + u * step + mp.rsub;
+      FE nf = (FE)fo[u];
+      nf -= sm[u];
+      if (mp.col == 0 && ii < N) f[ii] = nf;
+      const double fv = ii < N ? (double)nf : 0.0;
+      a0 = fma(x0[u], fv, a0);
+      a1 = fma(x1[u], fv, a1);
+    }
+  }
+  for (int m = mp.ne2; m < 64; m <<= 1) {
+    a0 += __shfl_xor(a0, m);
+    a1 += __shfl_xor(a1, m);
+  }
+  if (mp.ne2 == 64) {
+    if (mp.rsub == 0) red[wave * 64 + mp.col] = a0;
+    SYNC();
+    if (TID < 64 && 2 * TID < ne) y[2 * TID] = (red[TID] + red[64 + TID]) + (red[128 + TID] + red[192 + TID]);
+    SYNC();
+    if (mp.rsub == 0) red[wave * 64 + mp.col] = a1;
+    SYNC();
+    if (TID < 64 && 2 * TID + 1 < ne)
+      y[2 * TID + 1] = (red[TID] + red[64 + TID]) + (red[128 + TID] + red[192 + TID]);
+    SYNC();
+  } else {
+    if (mp.rsub == 0) {
+      red[wave * 64 + mp.col] = a0;
+      red[wave * 64 + 32 + mp.col] = a1;
+    }
+    SYNC();
+    if (TID < mp.ne2) {
+      const double s0 = (red[TID] + red[64 + TID]) + (red[128 + TID] + red[192 + TID]);
+      const double s1 = (red[32 + TID] + red[96 + TID]) + (red[160 + TID] + red[224 + TID]);
+      if (2 * TID < ne) y[2 * TID] = s0;
+      if (2 * TID + 1 < ne) y[2 * TID + 1] = s1;
+    }
+    SYNC();
+  }
+}
+template <typename PF>
+__device__ __forceinline__ void fock_subqt(const double *Q, int ne, int N, PF f, const double *z, double *y,
+                                           double *red) {
+  if ((ne & 1) == 0) fock_subqt_t<true>(Q, ne, N, f, z, y, red);
+  else fock_subqt_t<false>(Q, ne, N, f, z, y, red);
+}
+
 template <typename PF>
 __device__ __forceinline__ void fock_qt(const double *Q, int ne, int N, PF f, double *y, double *red) {
   if ((ne & 1) == 0) fock_qt_t<true>(Q, ne, N, f, y, red);
@@ -3031,8 +3294,13 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
       const double *gc = gcl, *gs = gsl;
       for (int a = TID; a < vs; a += kThreads) vsum[a] = 0.0;
       SYNC();
+      // the second pass's projection rides on the first pass's subtraction
+      // (fock_subqt: one read of Q_i fewer per level)
+      const bool fuse = !qcache && ne <= 128;
       for (int pass = 0; pass < 2 && m > 0; ++pass) {
-        if (qcache) {
+        if (fuse && pass == 1) {
+          // y holds Q^T w already
+        } else if (qcache) {
           // y = Q^T w: per-thread partial sums over own rows, then a block sum
           double yp[kFne];
 #pragma unroll
@@ -3114,6 +3382,9 @@ __device__ bool swap_move(const WalkerDesc &w, int sp, int k, int j, double xacc
               if (a < ne) s += qr[q][a] * z[a];
             if (i < N) fw[i] -= s;
           }
+        } else if (fuse && pass == 0) {
+          if (in_lds(fw)) fock_subqt(Q, ne, N, as_lds(fw), z, y, L.red);
+          else fock_subqt(Q, ne, N, fw, z, y, L.red);
         } else if (in_lds(fw)) {
           fock_sub(Q, ne, N, as_lds(fw), z);
         } else {
@@ -3432,6 +3703,256 @@ __global__ void __launch_bounds__(kThreads) k_swap_ratio(const WalkerDesc *__res
 static int clamp_mm(int mm) { return mm < 1 ? 1 : mm; }
 
 // allow dynamic LDS above the 64 KiB default
+
+// ---------------------------------------------------------------------------
+// Constrained-path (phaseless) inner walk of one Fock state eta (SM Sec. VI).
+// Each random walker propagates Phi = P_eta through B_l(s) = E_K D0 F_l(s),
+// drawing its Ising fields site by site against the backward trial state of
+// the one-body Hamiltonian, X_l = (B0_L ... B0_{l+1} E_K)^T P_eta: the left
+// stack of the U = 0 trial walker, stored at every slice's flip point.  The
+// overlap matrix X_l^T Phi does not change across E_K D0 (the trial state
+// moves back by the same factor), so the inverse carries over from slice to
+// slice and each site's ratio is the rank-1 one,
+//   r_sigma(s) = 1 + (e^{sigma lambda s} - 1) g_sigma,
+//   g_sigma = Phi[i,:] (X^T Phi)^{-1} X[i,:]^T,
+// followed by the Sherman-Morrison update of the inverse and the row scaling
+// Phi[i,:] *= e^{sigma lambda s}.  Phaseless cut: a factor max(0, r); a
+// walker whose factor is 0 is dead and draws nothing more.  Field draws:
+//   importance: p(+1) = max(0, r(+1)) / (max(0, r(+1)) + max(0, r(-1))),
+//               weight times (max(0, r(+1)) + max(0, r(-1))) / 2;
+//   free:       p(+1) = 1/2, weight times max(0, r(s)).
+// Walkers are QR'd at block ends (Phi -> Q; the scale cancels in every
+// ratio) and their inverse is formed afresh at block starts.
+// One workgroup per walker, inverses in LDS (Ne <= 64 per spin); the rows of
+// the next site are loaded while the current site's update runs.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_cp_init(const WalkerDesc *__restrict__ trial, CpDesc cp) {
+  const WalkerDesc &w = *trial;
+  const int a = blockIdx.x, N = w.N;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    double *ph = cp.cur.phi[sp] + (size_t)a * N * m;
+    for (size_t t = TID; t < (size_t)N * m; t += kThreads) ph[t] = 0.0;
+    __syncthreads();
+    for (int q = TID; q < m; q += kThreads) ph[(size_t)w.occ[sp][q] * m + q] = 1.0;
+  }
+  int8_t *path = cp.cur.s + (size_t)a * w.L * N;
+  for (size_t t = TID; t < (size_t)w.L * N; t += kThreads) path[t] = 0;
+  if (TID == 0) {
+    cp.cur.logw[a] = 0.0;
+    cp.cur.logq[a] = 0.0;
+    cp.cuts[a] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_cp_walk(const WalkerDesc *__restrict__ trial, CpDesc cp, LdsPlan pl,
+                                                      int l_begin, int l_end, uint32_t tag) {
+  const WalkerDesc &w = *trial;
+  const int a = blockIdx.x, N = w.N;
+  Lds L = carve(pl);
+  load_bonds(w, L, pl.bond_words);
+  if (cp.cur.logw[a] == -INFINITY) return;   // dead: the same value for every thread
+  const int ne[2] = {w.ne[0], w.ne[1]};
+  double *phi[2], *Ms[2] = {L.Ms0, L.Ms1};
+  for (int sp = 0; sp < 2; ++sp) phi[sp] = cp.cur.phi[sp] + (size_t)a * N * ne[sp];
+  int8_t *path = cp.cur.s + (size_t)a * w.L * N;
+  double *rows = L.vec;       // [2 buf][x0, p0, x1, p1][64]: rows of the current and the next site
+  double *uv = L.uw;          // [u0, v0, u1, v1][64]
+  double *cs = L.scal + 40;   // c0, c1, 1 + Delta0, 1 + Delta1, dead (slots the QR and inverse do not use)
+  // a segment that starts inside a block resumes with the stored inverse
+  if ((l_begin - 1) % w.nstab != 0)
+    for (int sp = 0; sp < 2; ++sp)
+      for (int t = TID; t < ne[sp] * ne[sp]; t += kThreads)
+        Ms[sp][t] = cp.cur.minv[sp][(size_t)a * ne[sp] * ne[sp] + t];
+  double logw = cp.cur.logw[a], logq = cp.cur.logq[a];   // thread 0's running sums
+  if (TID == 0) cs[4] = 0.0;
+  __syncthreads();
+  const int grp = TID >> 6, t = TID & 63, gsp = grp >> 1;
+  bool dead = false;
+  for (int l = l_begin; l <= l_end && !dead; ++l) {
+    const int k = (l - 1) / w.nstab + 1;
+    const int l0 = (k - 1) * w.nstab + 1, l1 = min(k * w.nstab, w.L);
+    const double *X[2];
+    for (int sp = 0; sp < 2; ++sp) {
+      X[sp] = w.LX[sp] + (size_t)(l - 1) * N * ne[sp];
+      apply_diag(w, phi[sp], ne[sp], l, sp, false);   // D0: the trial walker's lambda is 0
+    }
+    if (l == l0)
+      for (int sp = 0; sp < 2; ++sp) {
+        if (ne[sp] == 0) continue;
+        gram(X[sp], ne[sp], phi[sp], ne[sp], N, L.A, L.red);
+        double la;
+        int sg;
+        gj_inverse(L.A, Ms[sp], ne[sp], L, &la, &sg);
+      }
+    // rows of site 0: group grp (x0, p0, x1, p1) loads its row
+    {
+      const int m = ne[gsp];
+      const double *src = (grp & 1) ? phi[gsp] : X[gsp];
+      if (t < m) rows[grp * 64 + t] = src[t];
+    }
+    __syncthreads();
+    for (int i = 0; i < N; ++i) {
+      const double *rb = rows + (i & 1) * 256;
+      double *rn = rows + ((i + 1) & 1) * 256;
+      // u = M^{-1} x and v = p M^{-1}, one entry per thread
+      {
+        const int m = ne[gsp];
+        const double *M = Ms[gsp];
+        if (t < m) {
+          double acc = 0.0;
+          if ((grp & 1) == 0) {
+            const double *x = rb + gsp * 128;
+            for (int q = 0; q < m; ++q) acc += M[t * m + q] * x[q];
+          } else {
+            const double *pr = rb + gsp * 128 + 64;
+            for (int q = 0; q < m; ++q) acc += pr[q] * M[q * m + t];
+          }
+          uv[grp * 64 + t] = acc;
+        }
+      }
+      __syncthreads();
+      if (TID < 64) {
+        double g0 = t < ne[0] ? rb[64 + t] * uv[t] : 0.0;
+        double g1 = t < ne[1] ? rb[192 + t] * uv[128 + t] : 0.0;
+        g0 = wave_sum_d(g0);
+        g1 = wave_sum_d(g1);
+        if (TID == 0) {
+          double f[2];
+          for (int u = 0; u < 2; ++u) {
+            const double r = (1.0 + cp.delta[0][u] * g0) * (1.0 + cp.delta[1][u] * g1);
+            f[u] = r > 0.0 ? r : 0.0;
+          }
+          const double x = uniform01(cp.seed, (uint64_t)a, kCpField, tag, (uint32_t)(l - 1), (uint32_t)i);
+          int u = 0;
+          double factor = 0.0;
+          if (cp.mode == 0) {
+            const double Ni = 0.5 * f[0] + 0.5 * f[1];
+            if (Ni != 0.0) {
+              const double pp = 0.5 * f[0] / Ni;
+              u = x < pp ? 0 : 1;
+              factor = Ni;
+              logq += log(u == 0 ? pp : 1.0 - pp);
+            }
+          } else {
+            u = x < 0.5 ? 0 : 1;
+            factor = f[u];
+          }
+          if (factor == 0.0) {
+            cs[4] = 1.0;
+            logw = -INFINITY;
+          } else {
+            logw += log(factor);
+            path[(size_t)(l - 1) * N + i] = (int8_t)(u == 0 ? 1 : -1);
+            const double d0 = cp.delta[0][u], d1 = cp.delta[1][u];
+            cs[0] = d0 / (1.0 + d0 * g0);
+            cs[1] = d1 / (1.0 + d1 * g1);
+            cs[2] = 1.0 + d0;
+            cs[3] = 1.0 + d1;
+          }
+        }
+      }
+      __syncthreads();
+      if (cs[4] != 0.0) {
+        dead = true;
+        break;
+      }
+      // the next site's rows (its p row is not touched by this update)
+      if (i + 1 < N) {
+        const int m = ne[gsp];
+        const double *src = (grp & 1) ? phi[gsp] : X[gsp];
+        if (t < m) rn[grp * 64 + t] = src[(size_t)(i + 1) * m + t];
+      }
+      for (int sp = 0; sp < 2; ++sp) {
+        const int m = ne[sp];
+        const double c = cs[sp];
+        const double *u = uv + sp * 128, *v = uv + sp * 128 + 64;
+        for (int e = TID; e < m * m; e += kThreads) {
+          const int p = e / m, q = e - p * m;
+          Ms[sp][e] -= c * u[p] * v[q];
+        }
+        if (TID < m) phi[sp][(size_t)i * m + TID] *= cs[2 + sp];
+      }
+      __syncthreads();
+    }
+    if (dead) break;
+    for (int sp = 0; sp < 2; ++sp) apply_ek(w, L, phi[sp], ne[sp]);
+    if (l == l1)
+      for (int sp = 0; sp < 2; ++sp) {
+        const int m = ne[sp];
+        if (m == 0) continue;
+        cholqr<double>(phi[sp], cp.tmp[sp] + (size_t)a * N * m, phi[sp], nullptr, nullptr,
+                       cp.vacc + ((size_t)a * 2 + sp) * cp.mm * cp.mm, N, m, L, w.sc);
+      }
+  }
+  __syncthreads();
+  if (!dead)
+    for (int sp = 0; sp < 2; ++sp)
+      for (int e = TID; e < ne[sp] * ne[sp]; e += kThreads)
+        cp.cur.minv[sp][(size_t)a * ne[sp] * ne[sp] + e] = Ms[sp][e];
+  if (TID == 0) {
+    cp.cur.logw[a] = logw;
+    cp.cur.logq[a] = logq;
+    if (dead) cp.cuts[a] += 1;
+  }
+}
+
+// comb over the cumulative weights (one thread, in walker order): copy j
+// takes the walker whose interval holds (j + xi) W / nw (the nearest live
+// walker if rounding lands on a dead one's empty interval); log_pc gains the
+// log of the mean weight
+__global__ void __launch_bounds__(64) k_cp_comb(CpDesc cp, int l, uint32_t tag) {
+  if (threadIdx.x != 0) return;
+  const int nw = cp.nw;
+  double mx = -INFINITY;
+  for (int a = 0; a < nw; ++a) mx = fmax(mx, cp.cur.logw[a]);
+  if (mx == -INFINITY) {
+    for (int j = 0; j < nw; ++j) cp.pick[j] = -1;
+    return;
+  }
+  double W = 0.0;
+  for (int a = 0; a < nw; ++a) W += exp(cp.cur.logw[a] - mx);
+  const double xi = uniform01(cp.seed, 0, kCpComb, tag, (uint32_t)(l - 1), 0);
+  int a = 0;
+  double cum = exp(cp.cur.logw[0] - mx);
+  for (int j = 0; j < nw; ++j) {
+    const double tpos = ((double)j + xi) * W / (double)nw;
+    while (a < nw - 1 && cum <= tpos) {
+      ++a;
+      cum += exp(cp.cur.logw[a] - mx);
+    }
+    int b = a;
+    while (b > 0 && cp.cur.logw[b] == -INFINITY) --b;
+    while (b < nw - 1 && cp.cur.logw[b] == -INFINITY) ++b;
+    cp.pick[j] = b;
+  }
+  cp.log_pc[0] += mx + log(W / (double)nw);
+}
+
+// copy j of the comb: the state of walker pick[j] into slot j of dst, weight 1
+__global__ void __launch_bounds__(kThreads) k_cp_copy(const WalkerDesc *__restrict__ trial, CpDesc cp, CpState dst) {
+  const WalkerDesc &w = *trial;
+  const int j = blockIdx.x, src = cp.pick[j] < 0 ? j : cp.pick[j];
+  const int N = w.N;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = w.ne[sp];
+    const double *ps = cp.cur.phi[sp] + (size_t)src * N * m;
+    double *pd = dst.phi[sp] + (size_t)j * N * m;
+    for (size_t t = TID; t < (size_t)N * m; t += kThreads) pd[t] = ps[t];
+    const double *ms = cp.cur.minv[sp] + (size_t)src * m * m;
+    double *md = dst.minv[sp] + (size_t)j * m * m;
+    for (int t = TID; t < m * m; t += kThreads) md[t] = ms[t];
+  }
+  const int8_t *ss = cp.cur.s + (size_t)src * w.L * N;
+  int8_t *sd = dst.s + (size_t)j * w.L * N;
+  for (size_t t = TID; t < (size_t)w.L * N; t += kThreads) sd[t] = ss[t];
+  if (TID == 0) {
+    // every walker dead (pick < 0): the population is carried over as it is
+    dst.logw[j] = cp.pick[j] < 0 ? cp.cur.logw[j] : 0.0;
+    dst.logq[j] = cp.cur.logq[src];
+  }
+}
+
 // The dynamic-LDS limit of a kernel is raised once to the largest size asked
 // for; later launches (also those recorded into a graph) make no call.
 template <typename K>
@@ -3457,6 +3978,25 @@ hipError_t launch_init(const WalkerDesc *d, int draw_fields, int draw_occ, hipSt
 static LdsPlan clamp_plan(LdsPlan p) {
   p.mm = clamp_mm(p.mm);
   return p;
+}
+hipError_t launch_cp_init(const WalkerDesc *trial, CpDesc cp, hipStream_t st) {
+  hipLaunchKernelGGL(k_cp_init, dim3(cp.nw), dim3(kThreads), 0, st, trial, cp);
+  return hipGetLastError();
+}
+hipError_t launch_cp_walk(const WalkerDesc *trial, CpDesc cp, LdsPlan p, int l_begin, int l_end, uint32_t tag,
+                          hipStream_t st) {
+  p = clamp_plan(p);
+  const size_t b = lds_bytes(p);
+  lds_attr(k_cp_walk, b);
+  hipLaunchKernelGGL(k_cp_walk, dim3(cp.nw), dim3(kThreads), b, st, trial, cp, p, l_begin, l_end, tag);
+  return hipGetLastError();
+}
+hipError_t launch_cp_comb(CpDesc cp, CpState dst, const WalkerDesc *trial, int l, uint32_t tag, hipStream_t st) {
+  hipLaunchKernelGGL(k_cp_comb, dim3(1), dim3(64), 0, st, cp, l, tag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cp_copy, dim3(cp.nw), dim3(kThreads), 0, st, trial, cp, dst);
+  return hipGetLastError();
 }
 hipError_t launch_fresh_weight(const WalkerDesc *d, int n, LdsPlan p, int set_tracked, hipStream_t st) {
   p = clamp_plan(p);

@@ -34,7 +34,10 @@ EXPORTED = [
     "lecqmc_batch_create", "lecqmc_batch_sweep", "lecqmc_batch_destroy",
     "lecqmc_get_shape", "lecqmc_set_shape", "lecqmc_autotune", "lecqmc_ctx_query",
     "lecqmc_sweep_batch_static",
+    "lecqmc_cp_create", "lecqmc_cp_run", "lecqmc_cp_walker", "lecqmc_cp_stats", "lecqmc_cp_destroy",
 ]
+CP_IMPORTANCE = 0
+CP_FREE = 1
 STATIC_MAX_WALKERS = 1024
 
 
@@ -69,6 +72,7 @@ _lib = None
 _live_walkers: "weakref.WeakSet" = weakref.WeakSet()
 _live_batches: "weakref.WeakSet" = weakref.WeakSet()
 _live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+_live_cps: "weakref.WeakSet" = weakref.WeakSet()
 
 
 @atexit.register
@@ -77,6 +81,8 @@ def _release_all():
     walkers, then contexts)."""
     for b in list(_live_batches):
         b.close()
+    for cp in list(_live_cps):
+        cp.close()
     for w in list(_live_walkers):
         w.close()
     for c in list(_live_contexts):
@@ -132,6 +138,12 @@ def load():
             "lecqmc_set_shape": (C.c_int, [vp, i32, i32]),
             "lecqmc_autotune": (C.c_int, [C.POINTER(vp), i32, C.POINTER(i32), C.POINTER(i32),
                                           C.POINTER(C.c_double)]),
+            "lecqmc_cp_create": (C.c_int, [vp, C.POINTER(_Lattice), C.POINTER(_Params), vp, vp, i32, i32, i32,
+                                           C.POINTER(vp)]),
+            "lecqmc_cp_run": (C.c_int, [vp, C.c_uint32, C.POINTER(dbl)]),
+            "lecqmc_cp_walker": (C.c_int, [vp, i32, C.POINTER(dbl), C.POINTER(dbl), vp]),
+            "lecqmc_cp_stats": (C.c_int, [vp, C.POINTER(dbl), C.POINTER(i64), C.POINTER(i32)]),
+            "lecqmc_cp_destroy": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -184,6 +196,7 @@ class Context:
         self.device = device
         self._walkers = weakref.WeakSet()
         self._batches = weakref.WeakSet()
+        self._cps = weakref.WeakSet()
         _live_contexts.add(self)
 
     def synchronize(self):
@@ -213,6 +226,8 @@ class Context:
         if getattr(self, "h", None):
             for b in list(self._batches):
                 b.close()
+            for cp in list(self._cps):
+                cp.close()
             for w in list(self._walkers):
                 w.close()
             _check(load().lecqmc_ctx_destroy(self.h))
@@ -372,6 +387,55 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             load().lecqmc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CPWalk:
+    """Constrained-path inner walk of one Fock state (lecqmc_cp_*): a
+    population of random walkers on the GPU whose weights estimate
+    R(eta) = E_s[prod_sigma det(P^T B(s) P)] / W_T(eta) under the phaseless cut."""
+
+    def __init__(self, ctx: Context, lat, par, occ_up, occ_dn, n_walkers, mode=CP_IMPORTANCE, pc_every=0):
+        lib = load()
+        keep = []
+        self._lat, self._par = _marshal(lat, par, keep)
+        ou = np.ascontiguousarray(occ_up, dtype=np.int32)
+        od = np.ascontiguousarray(occ_dn, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib.lecqmc_cp_create(ctx.h, C.byref(self._lat), C.byref(self._par), ou.ctypes.data, od.ctypes.data,
+                                    n_walkers, mode, pc_every, C.byref(h)))
+        self.h = h
+        self.N, self.L, self.nw = lat.n_sites, par.L_tau, n_walkers
+        ctx._cps.add(self)
+        _live_cps.add(self)
+
+    def run(self, tag=0):
+        """One inner walk from Phi = P_eta; returns log of the estimate of R(eta)."""
+        lr = C.c_double()
+        _check(load().lecqmc_cp_run(self.h, tag, C.byref(lr)))
+        return lr.value
+
+    def walker(self, a):
+        """(log weight, sum of log p of its draws, field path [L][N]) of slot a."""
+        lw, lq = C.c_double(), C.c_double()
+        f = np.zeros((self.L, self.N), dtype=np.int8)
+        _check(load().lecqmc_cp_walker(self.h, a, C.byref(lw), C.byref(lq), f.ctypes.data))
+        return lw.value, lq.value, f
+
+    def stats(self):
+        lp, cuts, alive = C.c_double(), C.c_int64(), C.c_int32()
+        _check(load().lecqmc_cp_stats(self.h, C.byref(lp), C.byref(cuts), C.byref(alive)))
+        return {"log_pc": lp.value, "cuts": cuts.value, "alive": alive.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lecqmc_cp_destroy(self.h)
             self.h = None
 
     def __del__(self):
