@@ -1,10 +1,11 @@
 """Throughput of the canonical-ensemble DQMC hot path on one MI355X.
 
 Headline workload (value): the batched uneven walkers, 256 independent
-chains in one fixed batch, L x L periodic square lattices with L uniform in
-{16, 24, 32, 48, 64} (N = 256..4096), Ne per spin uniform in [4, 32], U
-uniform in [2, 6], beta in {8, 16}, dtau = 0.05, a QR every 10 slices, FP64,
-chain shapes autotuned, every sweep one HIP graph replay.  It is the largest
+chains, L x L periodic square lattices with L uniform in {16, 24, 32, 48, 64}
+(N = 256..4096), Ne per spin uniform in [4, 32], U uniform in [2, 6], beta in
+{8, 16}, dtau = 0.05, a QR every 10 slices, FP64, chain shapes autotuned.
+The walkers are split by cost into four groups with a stream and a HIP graph
+each, and the groups' sweeps run concurrently.  It is the largest
 fixed configuration that runs on one GPU.  A step is one full sweep of every
 walker: left-stack build, forward pass with N * L_tau Ising-flip attempts and
 QR stabilisation, and N_sigma particle-hole swaps per spin.
@@ -168,6 +169,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the headline batch (profiling of other legs)")
+    ap.add_argument("--groups", type=int, default=4, help="concurrent walker groups of the headline batch (1..4)")
     ap.add_argument("--no-dilute", action="store_true", help="skip the 32x32 dilute-gas objects")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-flat", action="store_true", help="skip the 128-walker flat-band batch")
@@ -198,55 +200,98 @@ def main():
 
 
 def headline(args, cfg):
+    """The 256-walker batch.  Walkers are sorted by cost (N L_tau Ne^2) and
+    split into `groups` contiguous groups, each with its own context, stream,
+    fixed batch and HIP graph of one sweep.  A step replays every group's
+    graph once; the groups' graphs run concurrently on their streams, so the
+    cheap walkers' phases overlap the expensive walkers' instead of waiting at
+    each phase for the slowest walker of the whole batch.  Every walker
+    advances exactly one sweep per step."""
     import torch
     from paper_2601_08552_amd import lecqmc
-    note("uneven batch: creating 256 walkers")
-    gs = torch.cuda.Stream()
-    gctx = lecqmc.Context(0, stream=gs)
-    ws = [lecqmc.Walker(gctx, lat, par) for lat, par in cfg]
-    note("uneven batch: autotuning")
+    G = max(1, min(4, args.groups))
+    cost = lambda c: cfg[c][0].n_sites * cfg[c][1].L_tau * max(cfg[c][1].n_up, cfg[c][1].n_dn) ** 2
+    order = sorted(range(len(cfg)), key=lambda c: -cost(c))
+    groups = [order[k * len(order) // G:(k + 1) * len(order) // G] for k in range(G)]
+    note(f"uneven batch: creating 256 walkers in {G} groups")
+    streams = [torch.cuda.Stream() for _ in range(G)]
+    ctxs = [lecqmc.Context(0, stream=st) for st in streams]
+    ws = [None] * len(cfg)
+    for g in range(G):
+        for c in groups[g]:
+            ws[c] = lecqmc.Walker(ctxs[g], *cfg[c])
+    note("uneven batch: autotuning (the groups concurrently, one host thread each)")
+    import threading
     t_tune = time.perf_counter()
-    tuned = lecqmc.autotune(ws)
+    res = [None] * G
+
+    def tune(g):
+        res[g] = lecqmc.autotune([ws[c] for c in groups[g]])
+
+    th = [threading.Thread(target=tune, args=(g,)) for g in range(G)]
+    for t_ in th:
+        t_.start()
+    for t_ in th:
+        t_.join()
+    tuned = [r for g in range(G) for r in res[g]]
     t_tune = time.perf_counter() - t_tune
-    # the forward-pass launch timed alone by the context's phase events (on
-    # the stream the kernels run on), then the batch captured into a graph
+    # each group's phases timed alone by its context's events (on the stream
+    # its kernels run on)
     note("uneven batch: phase timing")
-    lecqmc.sweep_batch(ws, 1)
-    gctx.synchronize()
-    gctx.set_timing(True)
-    gctx.phase_times()
-    lecqmc.sweep_batch(ws, 2)
-    ms_phase, cnt = gctx.phase_times()
-    gctx.set_timing(False)
-    batch = lecqmc.Batch(ws)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=gs):
-        batch.sweep(1)
+    ph = []
+    for g in range(G):
+        wg = [ws[c] for c in groups[g]]
+        lecqmc.sweep_batch(wg, 1)
+        ctxs[g].synchronize()
+        ctxs[g].set_timing(True)
+        ctxs[g].phase_times()
+        lecqmc.sweep_batch(wg, 2)
+        ms, cn = ctxs[g].phase_times()
+        ctxs[g].set_timing(False)
+        ph.append([ms[k] / max(cn[k], 1) for k in range(3)])
+    batches, graphs = [], []
+    for g in range(G):
+        b = lecqmc.Batch([ws[c] for c in groups[g]])
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=streams[g]):
+            b.sweep(1)
+        batches.append(b)
+        graphs.append(gr)
     torch.cuda.synchronize()
-    note(f"uneven batch: {args.warmup} warm-up + {args.steps} timed graph replays")
+    note(f"uneven batch: {args.warmup} warm-up + {args.steps} timed steps")
     for _ in range(args.warmup):
-        graph.replay()
+        for gr in graphs:
+            gr.replay()
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)] for _ in range(G)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with torch.cuda.stream(gs):
-        ev[0].record(gs)
-        for q in range(args.steps):
-            graph.replay()
-            ev[q + 1].record(gs)
+    for g in range(G):
+        ev[g][0].record(streams[g])
+    for q in range(args.steps):
+        for g in range(G):
+            with torch.cuda.stream(streams[g]):
+                graphs[g].replay()
+            ev[g][q + 1].record(streams[g])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_ms = [ev[q].elapsed_time(ev[q + 1]) for q in range(args.steps)]
+    # per-walker sweep latency: its group's step times
+    lat_ms = []
+    for g in range(G):
+        for q in range(args.steps):
+            lat_ms += [ev[g][q].elapsed_time(ev[g][q + 1])] * len(groups[g])
     upd_sweep = sum(lat.n_sites * par.L_tau for lat, par in cfg)
     value = upd_sweep * args.steps / wall
-    fwd_ms = ms_phase[1] / max(cnt[1], 1)
-    alg = sum(algorithmic_bytes_forward(lat.n_sites, par.n_up, par.n_dn, par.L_tau, par.n_stab) for lat, par in cfg)
+    alg_g = [sum(algorithmic_bytes_forward(cfg[c][0].n_sites, cfg[c][1].n_up, cfg[c][1].n_dn, cfg[c][1].L_tau,
+                                           cfg[c][1].n_stab) for c in groups[g]) for g in range(G)]
+    fwd_ms = sum(p[1] for p in ph) / G
+    alg = sum(alg_g) / G
     achieved = alg / (fwd_ms * 1e-3) / 1e9
     fwd_w = sorted(r[2] for r in tuned)
     st0 = ws[0].stats()
-    hbm_gib = gctx.bytes_in_use() / 2**30
-    batch.close()
+    hbm_gib = sum(cx.bytes_in_use() for cx in ctxs) / 2**30
+    for b in batches:
+        b.close()
     out = {
         "metric": METRIC,
         "value": value,
@@ -262,12 +307,13 @@ def headline(args, cfg):
         "data": "synthetic",
         "config": {"workload": "batched uneven walkers: 256 chains, L x L periodic square, L in {16,24,32,48,64}, "
                                "Ne per spin in [4,32], U in [2,6], beta in {8,16}, dtau=0.05, QR every 10 slices, "
-                               "FP64, autotuned chain shapes, sweeps replayed from a HIP graph",
-                   "walkers": len(ws), "updates_per_sweep": upd_sweep, "hbm_gib": hbm_gib},
-        "latency_ms": {**pct(step_ms), "note": "per-walker sweep latency = batched step time (every walker "
-                                                "advances one sweep per step)"},
-        "phase_ms_per_launch": {"left_stack": ms_phase[0] / max(cnt[0], 1), "forward": fwd_ms,
-                                "fock": ms_phase[2] / max(cnt[2], 1)},
+                               "FP64, autotuned chain shapes, sweeps replayed from HIP graphs",
+                   "walkers": len(ws), "updates_per_sweep": upd_sweep, "hbm_gib": hbm_gib,
+                   "groups": G, "note": "walkers sorted by N*L_tau*Ne^2 into contiguous groups, one stream and one "
+                                        "graph per group, the groups' sweeps concurrent"},
+        "latency_ms": {**pct(lat_ms), "note": "per-walker sweep latency = its group's step time"},
+        "phase_ms_per_launch": {"left_stack": [p[0] for p in ph], "forward": [p[1] for p in ph],
+                                "fock": [p[2] for p in ph], "note": "per group, each group alone"},
         "autotune": {"seconds": t_tune,
                      "shapes": {f"{t},{c}": sum(1 for r in tuned if r[:2] == (t, c))
                                 for (t, c) in sorted({r[:2] for r in tuned})},
@@ -275,8 +321,9 @@ def headline(args, cfg):
         "roofline": {"bound": "hbm", "kernel": "k_forward", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg,
-                     "note": "one launch = the forward pass of all 256 walkers; it lasts as long as its slowest "
-                             "walker (the dependent flip chain), not as long as its bytes take"},
+                     "note": "one launch = the forward pass of one group's walkers (average over the groups); it "
+                             "lasts as long as the group's slowest walker (the dependent flip chain), not as long "
+                             "as its bytes take"},
         "stats_walker0": {k: st0[k] for k in ("logw_drift", "max_wrap_err", "qr_shifted")},
     }
     traffic = measured_traffic(os.path.join(ROOT, "paper_2601_08552_amd", "csrc", "lecqmc_kernels.hip"),
@@ -284,7 +331,8 @@ def headline(args, cfg):
     out["roofline"]["traffic"] = traffic
     for w in ws:
         w.close()
-    gctx.close()
+    for cx in ctxs:
+        cx.close()
     return out
 
 

@@ -3716,7 +3716,8 @@ static int clamp_mm(int mm) { return mm < 1 ? 1 : mm; }
 //   r_sigma(s) = 1 + (e^{sigma lambda s} - 1) g_sigma,
 //   g_sigma = Phi[i,:] (X^T Phi)^{-1} X[i,:]^T,
 // followed by the Sherman-Morrison update of the inverse and the row scaling
-// Phi[i,:] *= e^{sigma lambda s}.  Phaseless cut: a factor max(0, r); a
+// Phi[i,:] *= e^{sigma lambda s} (two barriers per site: every wave takes the
+// decision itself from the same values).  Phaseless cut: a factor max(0, r); a
 // walker whose factor is 0 is dead and draws nothing more.  Field draws:
 //   importance: p(+1) = max(0, r(+1)) / (max(0, r(+1)) + max(0, r(-1))),
 //               weight times (max(0, r(+1)) + max(0, r(-1))) / 2;
@@ -3758,14 +3759,12 @@ __global__ void __launch_bounds__(kThreads) k_cp_walk(const WalkerDesc *__restri
   int8_t *path = cp.cur.s + (size_t)a * w.L * N;
   double *rows = L.vec;       // [2 buf][x0, p0, x1, p1][64]: rows of the current and the next site
   double *uv = L.uw;          // [u0, v0, u1, v1][64]
-  double *cs = L.scal + 40;   // c0, c1, 1 + Delta0, 1 + Delta1, dead (slots the QR and inverse do not use)
   // a segment that starts inside a block resumes with the stored inverse
   if ((l_begin - 1) % w.nstab != 0)
     for (int sp = 0; sp < 2; ++sp)
       for (int t = TID; t < ne[sp] * ne[sp]; t += kThreads)
         Ms[sp][t] = cp.cur.minv[sp][(size_t)a * ne[sp] * ne[sp] + t];
   double logw = cp.cur.logw[a], logq = cp.cur.logq[a];   // thread 0's running sums
-  if (TID == 0) cs[4] = 0.0;
   __syncthreads();
   const int grp = TID >> 6, t = TID & 63, gsp = grp >> 1;
   bool dead = false;
@@ -3812,51 +3811,52 @@ __global__ void __launch_bounds__(kThreads) k_cp_walk(const WalkerDesc *__restri
         }
       }
       __syncthreads();
-      if (TID < 64) {
+      // every wave forms g and takes the decision from the same LDS values in
+      // the same order, so every thread holds the same result and no barrier
+      // is needed before the update
+      double c0 = 0.0, c1 = 0.0, f0 = 1.0, f1 = 1.0;
+      {
         double g0 = t < ne[0] ? rb[64 + t] * uv[t] : 0.0;
         double g1 = t < ne[1] ? rb[192 + t] * uv[128 + t] : 0.0;
         g0 = wave_sum_d(g0);
         g1 = wave_sum_d(g1);
-        if (TID == 0) {
-          double f[2];
-          for (int u = 0; u < 2; ++u) {
-            const double r = (1.0 + cp.delta[0][u] * g0) * (1.0 + cp.delta[1][u] * g1);
-            f[u] = r > 0.0 ? r : 0.0;
+        double f[2];
+        for (int u = 0; u < 2; ++u) {
+          const double r = (1.0 + cp.delta[0][u] * g0) * (1.0 + cp.delta[1][u] * g1);
+          f[u] = r > 0.0 ? r : 0.0;
+        }
+        const double x = uniform01(cp.seed, (uint64_t)a, kCpField, tag, (uint32_t)(l - 1), (uint32_t)i);
+        int u = 0;
+        double factor = 0.0, pq = 1.0;
+        if (cp.mode == 0) {
+          const double Ni = 0.5 * f[0] + 0.5 * f[1];
+          if (Ni != 0.0) {
+            const double pp = 0.5 * f[0] / Ni;
+            u = x < pp ? 0 : 1;
+            factor = Ni;
+            pq = u == 0 ? pp : 1.0 - pp;
           }
-          const double x = uniform01(cp.seed, (uint64_t)a, kCpField, tag, (uint32_t)(l - 1), (uint32_t)i);
-          int u = 0;
-          double factor = 0.0;
-          if (cp.mode == 0) {
-            const double Ni = 0.5 * f[0] + 0.5 * f[1];
-            if (Ni != 0.0) {
-              const double pp = 0.5 * f[0] / Ni;
-              u = x < pp ? 0 : 1;
-              factor = Ni;
-              logq += log(u == 0 ? pp : 1.0 - pp);
-            }
-          } else {
-            u = x < 0.5 ? 0 : 1;
-            factor = f[u];
-          }
-          if (factor == 0.0) {
-            cs[4] = 1.0;
-            logw = -INFINITY;
-          } else {
+        } else {
+          u = x < 0.5 ? 0 : 1;
+          factor = f[u];
+        }
+        if (factor == 0.0) {
+          dead = true;
+          if (TID == 0) logw = -INFINITY;
+        } else {
+          if (TID == 0) {
             logw += log(factor);
+            if (cp.mode == 0) logq += log(pq);
             path[(size_t)(l - 1) * N + i] = (int8_t)(u == 0 ? 1 : -1);
-            const double d0 = cp.delta[0][u], d1 = cp.delta[1][u];
-            cs[0] = d0 / (1.0 + d0 * g0);
-            cs[1] = d1 / (1.0 + d1 * g1);
-            cs[2] = 1.0 + d0;
-            cs[3] = 1.0 + d1;
           }
+          const double d0 = cp.delta[0][u], d1 = cp.delta[1][u];
+          c0 = d0 / (1.0 + d0 * g0);
+          c1 = d1 / (1.0 + d1 * g1);
+          f0 = 1.0 + d0;
+          f1 = 1.0 + d1;
         }
       }
-      __syncthreads();
-      if (cs[4] != 0.0) {
-        dead = true;
-        break;
-      }
+      if (dead) break;
       // the next site's rows (its p row is not touched by this update)
       if (i + 1 < N) {
         const int m = ne[gsp];
@@ -3865,13 +3865,13 @@ __global__ void __launch_bounds__(kThreads) k_cp_walk(const WalkerDesc *__restri
       }
       for (int sp = 0; sp < 2; ++sp) {
         const int m = ne[sp];
-        const double c = cs[sp];
+        const double c = sp == 0 ? c0 : c1;
         const double *u = uv + sp * 128, *v = uv + sp * 128 + 64;
         for (int e = TID; e < m * m; e += kThreads) {
           const int p = e / m, q = e - p * m;
           Ms[sp][e] -= c * u[p] * v[q];
         }
-        if (TID < m) phi[sp][(size_t)i * m + TID] *= cs[2 + sp];
+        if (TID < m) phi[sp][(size_t)i * m + TID] *= sp == 0 ? f0 : f1;
       }
       __syncthreads();
     }
