@@ -588,14 +588,58 @@ __device__ bool cholesky(double *A, int m, double *scal) {
     const double r = A[j * m + j];
     for (int c = j + 1 + TID; c < m; c += kThreads) A[j * m + c] /= r;
     SYNC();
-    const int rem = m - j - 1;
-    for (int t = TID; t < rem * rem; t += kThreads) {
-      const int a = j + 1 + t / rem, c = j + 1 + t % rem;
-      if (c >= a) A[a * m + c] -= A[j * m + a] * A[j * m + c];
+    // trailing update, eight elements per thread and round with every load
+    // before any store (row j is not written here); one element per thread
+    // when they all fit in one round
+    const int rem = m - j - 1, tot = rem * rem;
+    if (tot <= kThreads) {
+      if (TID < tot) {
+        const int a = j + 1 + TID / rem, c = j + 1 + TID % rem;
+        if (c >= a) A[a * m + c] -= A[j * m + a] * A[j * m + c];
+      }
+      SYNC();
+      continue;
+    }
+    for (int t0 = TID; t0 < tot; t0 += 8 * kThreads) {
+      double x[8], ra[8], rc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * kThreads, tc = t < tot ? t : 0;
+        const int a = j + 1 + tc / rem, c = j + 1 + tc % rem;
+        x[u] = A[a * m + c];
+        ra[u] = A[j * m + a];
+        rc[u] = A[j * m + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * kThreads;
+        const int a = j + 1 + t / (rem > 0 ? rem : 1), c = j + 1 + t % (rem > 0 ? rem : 1);
+        if (t < tot && c >= a) A[a * m + c] = x[u] - ra[u] * rc[u];
+      }
     }
     SYNC();
   }
   return true;
+}
+
+// sum_{b = b0 .. b1} A[b] * B[b * sb], accumulated in order b0, b0 + 1, ...;
+// the operands of eight terms are loaded before they are added, so that the
+// loads of a matrix in device memory overlap
+__device__ __forceinline__ double dot_in_order(const double *A, const double *B, int sb, int b0, int b1) {
+  double s = 0.0;
+  int b = b0;
+  for (; b + 7 <= b1; b += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = A[b + u];
+      y[u] = B[(size_t)(b + u) * sb];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u] * y[u];
+  }
+  for (; b <= b1; ++b) s += A[b] * B[(size_t)b * sb];
+  return s;
 }
 
 // Ri = R^{-1} (upper triangular), column by column
@@ -604,8 +648,7 @@ __device__ void tri_inverse(const double *R, int m, double *Ri) {
     for (int a = c + 1; a < m; ++a) Ri[a * m + c] = 0.0;
     Ri[c * m + c] = 1.0 / R[c * m + c];
     for (int a = c - 1; a >= 0; --a) {
-      double s = 0.0;
-      for (int b = a + 1; b <= c; ++b) s += R[a * m + b] * Ri[b * m + c];
+      const double s = dot_in_order(R + a * m, Ri + c, m, a + 1, c);
       Ri[a * m + c] = -s / R[a * m + a];
     }
   }
@@ -753,8 +796,7 @@ __device__ bool cholqr_inplace(double *X, double *out2, double *Vout, double *Va
   tri_mul_rows<MR>(X, out2, N, m, L.B);
   for (int t = TID; t < m * m; t += kThreads) {
     const int a = t / m, c = t % m;
-    double s = 0.0;
-    for (int b = a; b <= c; ++b) s += L.A[a * m + b] * Vacc[b * m + c];
+    const double s = c >= a ? dot_in_order(L.A + a * m, Vacc + c, m, a, c) : 0.0;
     L.B[t] = c >= a ? s : 0.0;
   }
   SYNC();
@@ -827,8 +869,7 @@ __device__ __forceinline__ double cholqr(const F *Phi, double *tmp, double *q1, 
     // Vacc <- R_pass * Vacc (both upper triangular) via B
     for (int t = TID; t < m * m; t += kThreads) {
       const int a = t / m, c = t % m;
-      double s = 0.0;
-      for (int b = a; b <= c; ++b) s += L.A[a * m + b] * Vacc[b * m + c];
+      const double s = c >= a ? dot_in_order(L.A + a * m, Vacc + c, m, a, c) : 0.0;
       L.B[t] = c >= a ? s : 0.0;
     }
     SYNC();
@@ -861,15 +902,39 @@ __device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logab
   SYNC();
   double *fac = L.vec + 7 * L.vs;
   for (int c = 0; c < m; ++c) {
-    if (TID == 0) {
-      int p = c;
-      double best = fabs(M[c * m + c]);
-      for (int r = c + 1; r < m; ++r)
-        if (fabs(M[r * m + c]) > best) { best = fabs(M[r * m + c]); p = r; }
-      L.iscal[0] = p;
-      L.scal[1] = M[p * m + c];
-      if (best == 0.0) L.iscal[2] = 1;
-      if (p != c) L.iscal[1] = -L.iscal[1];
+    if (m <= 32) {
+      // short columns: one thread scans them in order
+      if (TID == 0) {
+        int p = c;
+        double best = fabs(M[c * m + c]);
+        for (int r = c + 1; r < m; ++r)
+          if (fabs(M[r * m + c]) > best) { best = fabs(M[r * m + c]); p = r; }
+        L.iscal[0] = p;
+        L.scal[1] = M[p * m + c];
+        if (best == 0.0) L.iscal[2] = 1;
+        if (p != c) L.iscal[1] = -L.iscal[1];
+      }
+    } else if (TID < 64) {
+      // the first row (in row order) of largest |M[r][c]|, r >= c: each lane
+      // scans rows c + lane, c + lane + 64, ... in order, then the wave keeps
+      // the larger value and, on a tie, the lower row
+      double best = -1.0;
+      int p = m;
+      for (int r = c + TID; r < m; r += 64) {
+        const double v = fabs(M[r * m + c]);
+        if (v > best) { best = v; p = r; }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int op = __shfl_xor(p, off);
+        if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+      }
+      if (TID == 0) {
+        L.iscal[0] = p;
+        L.scal[1] = M[p * m + c];
+        if (best == 0.0) L.iscal[2] = 1;
+        if (p != c) L.iscal[1] = -L.iscal[1];
+      }
     }
     SYNC();
     if (L.iscal[2]) { SYNC(); *logabs = -INFINITY; *sign = 0; return false; }
@@ -890,11 +955,29 @@ __device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logab
     SYNC();
     for (int r = TID; r < m; r += kThreads) fac[r] = M[r * m + c];
     SYNC();
-    for (int t = TID; t < m * m; t += kThreads) {
-      const int r = t / m, x = t % m;
-      if (r == c) continue;
-      M[r * m + x] -= fac[r] * M[c * m + x];
-      Minv[r * m + x] -= fac[r] * Minv[c * m + x];
+    // eight elements per thread and round: every load before any store
+    // (no element of the pivot row is written in this step)
+    const int tot = m * m;
+    for (int t0 = TID; t0 < tot; t0 += 8 * kThreads) {
+      double a[8], b[8], pa[8], pb[8], f[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * kThreads, tc = t < tot ? t : 0;
+        const int r = tc / m, x = tc - r * m;
+        a[u] = M[tc];
+        b[u] = Minv[tc];
+        pa[u] = M[c * m + x];
+        pb[u] = Minv[c * m + x];
+        f[u] = fac[r];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * kThreads;
+        if (t < tot && t / m != c) {
+          M[t] = a[u] - f[u] * pa[u];
+          Minv[t] = b[u] - f[u] * pb[u];
+        }
+      }
     }
     SYNC();
   }
