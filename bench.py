@@ -325,6 +325,10 @@ def headline(args, cfg):
                              "lasts as long as the group's slowest walker (the dependent flip chain), not as long "
                              "as its bytes take"},
         "stats_walker0": {k: st0[k] for k in ("logw_drift", "max_wrap_err", "qr_shifted")},
+        "near_ties": {"count": sum(w.stats()["near_ties"] for w in ws),
+                      "decisions": sum(w.stats()["flip_attempts"] + w.stats()["swap_attempts"] for w in ws),
+                      "note": "flip and swap decisions of all walkers so far whose uniform lay within 1e-9 of |r| "
+                              "(a rounding change of r that size could reverse them)"},
     }
     traffic = measured_traffic(os.path.join(ROOT, "paper_2601_08552_amd", "csrc", "lecqmc_kernels.hip"),
                                os.path.join(ROOT, "profiles", "k_forward_batched256_pmc.json"))
@@ -488,7 +492,8 @@ def run_legs(args, cfg, out):
             acc[name] = {"N": lat.n_sites, "ne": [par.n_up, par.n_dn], "L_tau": par.L_tau,
                          "fresh_logw_rel_err": abs(lf - lo) / max(1.0, abs(lo)),
                          "chain_identical_after_sweep": bool(same),
-                         "tracked_logw_rel_err_after_sweep": abs(lt - lto) / max(1.0, abs(lto))}
+                         "tracked_logw_rel_err_after_sweep": abs(lt - lto) / max(1.0, abs(lto)),
+                         "near_ties": {"gpu": g.stats()["near_ties"], "oracle": o.stats()["near_ties"]}}
             g.close()
         out["accuracy"] = acc
     ctx.close()

@@ -103,6 +103,9 @@ typedef struct {
   double logw_drift;                     /* max |tracked - fresh| log W at beta */
   int64_t qr_shifted;                    /* QR calls that needed the shifted retry */
   uint64_t sweeps;                       /* sweep counter                       */
+  int64_t near_ties;                     /* flip and swap decisions u < |r| with
+                                            |u - |r|| < 1e-9: a rounding change of r
+                                            that size could have reversed them   */
 } lecqmc_sweep_stats;
 
 /* Context: device ordinal, a borrowed hipStream_t (NULL = the library makes

@@ -50,7 +50,7 @@ class _Par(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("flip_attempts", C.c_int64), ("flip_accepts", C.c_int64),
                 ("swap_attempts", C.c_int64), ("swap_accepts", C.c_int64),
-                ("max_wrap_err", C.c_double), ("logw_drift", C.c_double)]
+                ("max_wrap_err", C.c_double), ("logw_drift", C.c_double), ("near_ties", C.c_int64)]
 
 
 _lib = None

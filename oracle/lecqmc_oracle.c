@@ -836,6 +836,7 @@ static void one_sweep(orc_walker *w, int do_measure) {
           double ratio = r[0] * r[1];
           double xr = orc_uniform(w->seed, w->wid, ORC_S_FLIP, sw, (uint32_t)(l - 1), (uint32_t)i);
           w->st.flip_attempts++;
+          if (fabs(xr - fabs(ratio)) < 1e-9) w->st.near_ties++;
           if (xr < fabs(ratio)) {
             w->st.flip_accepts++;
             for (int sp = 0; sp < 2; ++sp) {
@@ -939,6 +940,7 @@ static void one_sweep(orc_walker *w, int do_measure) {
         swap_compute(w, sp, k, j, &x);
         double xr = orc_uniform(w->seed, w->wid, ORC_S_SWAP_ACC, sw, (uint32_t)sp, (uint32_t)mm);
         w->st.swap_attempts++;
+        if (!x.zero && fabs(xr - exp(x.log_abs_r)) < 1e-9) w->st.near_ties++;
         if (!x.zero && xr < exp(x.log_abs_r)) {
           w->st.swap_accepts++;
           swap_commit(w, sp, &x);

@@ -56,6 +56,7 @@ typedef struct {
   int64_t swap_attempts, swap_accepts;
   double max_wrap_err;       /* max_i |A_wrap_ii - A_fresh_ii| at block starts */
   double logw_drift;         /* |tracked log W - fresh log W| at tau = beta */
+  int64_t near_ties;         /* flip and swap decisions with |u - |r|| < 1e-9 */
 } orc_stats;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */

@@ -1117,6 +1117,7 @@ extern "C" int lecqmc_get_stats(lecqmc_walker *w, lecqmc_sweep_stats *st) {
   st->logw_drift = sc.logw_drift;
   st->qr_shifted = sc.qr_shifted;
   st->sweeps = sc.sweep;
+  st->near_ties = sc.near_ties + sc.swap_near[0] + sc.swap_near[1];
   return rc;
 }
 

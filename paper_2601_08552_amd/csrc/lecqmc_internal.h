@@ -37,6 +37,8 @@ struct Scalars {
                                 // breakdown, bit 3 = wrap error of a measuring sweep above wrap_tol
   long long flip_att, flip_acc, qr_shifted;
   long long swap_att[2], swap_acc[2];   // per spin (one Fock workgroup per spin)
+  long long near_ties;          // flip decisions with |u - |r|| below the near-tie margin
+  long long swap_near[2];       // the same for swaps, per spin
   double fock_logw[2];          // log|r| of accepted swaps per spin, folded in by the next forward pass
   int fock_sign[2];
   double max_wrap, logw_drift;

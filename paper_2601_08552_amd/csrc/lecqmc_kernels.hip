@@ -1,12 +1,15 @@
 // gfx950 kernels of the canonical-ensemble DQMC hot path.
 //
-// One workgroup of 256 threads (4 wave64) owns one walker for the whole of a
-// phase; a batch launch gives every walker its own workgroup, so walkers of
-// different shapes share one launch.  Slater blocks (N x Ne, row-major FP64)
-// live in device memory and are streamed through L1/L2 by all 256 threads;
-// the Ne x Ne inverses (P^T B P)^{-1} stay in LDS during the forward pass,
-// where one wave runs the sequential Ising-flip chain (both spin species in
-// the two halves of the wave).
+// One workgroup of 256 threads (4 wave64) owns one walker (or one spin of a
+// walker) for the whole of a phase; a batch launch gives every walker its own
+// workgroup(s), so walkers of different shapes share one launch.  In the
+// forward pass the right Slater blocks Phi_R (N x Ne, row-major) stay in LDS
+// when they fit, and the left blocks are streamed from device memory in
+// staged chunks of sites.  One wave runs the sequential Ising-flip chain,
+// both spin species in the two halves of the wave: for Ne <= 32 the Ne x Ne
+// inverses (P^T B P)^{-1} are held in that wave's registers, above that in
+// LDS or device memory with delayed (Woodbury) updates on the FP64 matrix
+// cores.  The other three waves stage the next chunk meanwhile.
 //
 // Method (arXiv 2601.08552): weight of main text Eq. (1); HS-field updates
 // with the rank-1 fast update of the PQMC-like sweep (main text, "Ensemble
@@ -399,7 +402,7 @@ __device__ void apply_ekT(const WalkerDesc &w, const Lds &L, F *X, int m) {
 }
 // X <- D_l^{+-1} X for spin sp (l = 1..L)
 template <typename F>
-__device__ void apply_diag(const WalkerDesc &w, F *X, int m, int l, int sp, bool inverse) {
+__device__ __noinline__ void apply_diag(const WalkerDesc &w, F *X, int m, int l, int sp, bool inverse) {
   if (in_lds(X)) diag_t(w, as_lds(X), m, l, sp, inverse);
   else diag_t(w, X, m, l, sp, inverse);
 }
@@ -896,7 +899,7 @@ __device__ __forceinline__ double cholqr(const F *Phi, double *tmp, double *q1, 
 // Inverse by Gauss-Jordan elimination with partial pivoting.
 // M (LDS, m x m) is destroyed; Minv may be LDS or global.  log|det|, sign
 // and a singular flag are returned through scal / iscal.
-__device__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logabs, int *sign) {
+__device__ __noinline__ bool gj_inverse(double *M, double *Minv, int m, Lds &L, double *logabs, int *sign) {
   for (int t = TID; t < m * m; t += kThreads) Minv[t] = (t / m == t % m) ? 1.0 : 0.0;
   if (TID == 0) { L.scal[2] = 0.0; L.iscal[1] = 1; L.iscal[2] = 0; }
   SYNC();
@@ -1065,7 +1068,18 @@ struct ChainAcc {
   double prod;
   int expo;
   long long nacc;
+  int nnear;   // decisions whose uniform lies within kNearTie of |r|
 };
+// A decision u < |r| is counted as a near tie when |u - |r|| < kNearTie: a
+// rounding difference in r that large could have reversed it.
+constexpr double kNearTie = 1e-9;
+__device__ __forceinline__ int near_tie_lane(double u, double absr) { return fabs(u - absr) < kNearTie ? 1 : 0; }
+// In the chain wave u and |r| are the same in every lane: the tests go to
+// wave masks, so that the decision and the count stay scalar.
+__device__ __forceinline__ int near_tie(double u, double absr) {
+  return __ballot(fabs(u - absr) < kNearTie) != 0ull ? 1 : 0;
+}
+__device__ __forceinline__ bool accept_site(double u, double absr) { return __ballot(u < absr) != 0ull; }
 // prod stays in [1/2, 1): the exponent of every product is moved into expo
 __device__ __forceinline__ void acc_ratio(ChainAcc &acc, double r) {
   const double pr = acc.prod * r;
@@ -1141,8 +1155,9 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
     }
     const double rsp = fma(delta, a, 1.0);
     const double ratio = halves_product(rsp);
+    acc.nnear += near_tie(R.u, fabs(ratio));
     // ratio and the uniform are identical in every lane: a scalar branch
-    if (__builtin_amdgcn_readfirstlane((int)(R.u < fabs(ratio)))) {
+    if (accept_site(R.u, fabs(ratio))) {
       const double c = div_nr(delta, rsp);
 #pragma unroll
       for (int i = 0; i < 2 * T; ++i) {
@@ -1252,7 +1267,8 @@ __device__ unsigned chain_chunk_lds(const WalkerDesc &w, Lds &L, const double *x
     for (int o = 16; o >= 1; o >>= 1) part += __shfl_xor(part, o);
     const double rsp = 1.0 + delta * part;
     const double ratio = lane_read(rsp, 0) * lane_read(rsp, 32);
-    if (usb[r] < fabs(ratio)) {
+    acc.nnear += near_tie(usb[r], fabs(ratio));
+    if (accept_site(usb[r], fabs(ratio))) {
 #pragma unroll 1
       for (int col = h; col < m; col += 32) wsh[col] = dot8(M + col, m, pr, m);
       wave_fence();
@@ -1412,8 +1428,9 @@ __device__ __forceinline__ unsigned delayed_chain(const WalkerDesc &w, Lds &L, c
     const double delta = dsb[r];
     const double rsp = fma(delta, (double)G[r * kDS + r], 1.0);
     const double ratio = halves_product(rsp);
+    acc.nnear += near_tie(usb[r], fabs(ratio));
     // ratio and the uniform are identical in every lane: a scalar decision
-    if (__builtin_amdgcn_readfirstlane((int)(usb[r] < fabs(ratio)))) {
+    if (accept_site(usb[r], fabs(ratio))) {
       const double c = div_nr(delta, rsp);
       if (j < cnt) {
         const double grow = G[r * kDS + j], gcol = G[j * kDS + r];
@@ -1656,6 +1673,7 @@ __device__ __forceinline__ void mf_front(const WalkerDesc &w, const MfBufs &B, P
 struct MfSweep {
   double a[8];
   unsigned mask;
+  int nnear;
   double prod;   // accepted-ratio product of the chunk, renormalised as in acc_ratio
   int expo;
 };
@@ -1685,7 +1703,8 @@ __device__ __forceinline__ void mf_site(MfSweep &S, int sp, int h, int j, double
     const double pu = lane_read(S.a[QR], 16 * HR + R), pd = lane_read(S.a[QR], 32 + 16 * HR + R);
     const double ratio = pu * pd;
     const double ur = lane_read(uu, R);
-    if (__builtin_amdgcn_readfirstlane((int)(ur < fabs(ratio)))) {
+    S.nnear += near_tie(ur, fabs(ratio));
+    if (accept_site(ur, fabs(ratio))) {
       const double pinv = div_nr(1.0, sp ? pd : pu);
       // row R of this lane's column (held by the half HR)
       const unsigned lo = (unsigned)__double2loint(S.a[QR]), hi = (unsigned)__double2hiint(S.a[QR]);
@@ -1731,6 +1750,7 @@ __device__ __forceinline__ unsigned mf_decide(const MfBufs &B, const double *usb
   }
   const double uu = j < cnt ? usb[j] : 2.0;
   st.mask = 0u;
+  st.nnear = 0;
   st.prod = 1.0;
   st.expo = 0;
   // the chunk's sites run from registers: the caller's accumulator is
@@ -1739,6 +1759,7 @@ __device__ __forceinline__ unsigned mf_decide(const MfBufs &B, const double *usb
   const unsigned mask = st.mask;
   acc_ratio(acc, st.prod);
   acc.expo += st.expo;
+  acc.nnear += st.nnear;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int row = 8 * h + q;
@@ -2000,8 +2021,8 @@ __device__ void flush_chunk(const WalkerDesc &w, Lds &L, int l, int i0, int bufi
 // been applied and Ms0/Ms1 hold the fresh inverse at the flip point of l0;
 // on exit Ms0/Ms1 hold the updated inverse and phi = B_k ... applied.
 template <int T, typename F>
-__device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2],
-                              bool resident, int mm, ChainAcc &acc) {
+__device__ __forceinline__ void forward_block_body(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2],
+                                                   bool resident, int mm, ChainAcc &acc) {
   constexpr bool kReg = T > 0 && T != kDelayed && T != kMfma;   // register-tiled inverse
   // chains that stage D_l with the streamed rows (T = 1 serves Ne <= 8, whose
   // blocks nearly always stay resident, and keeps the staging it had)
@@ -2175,6 +2196,11 @@ __device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L
     }
   }
   SYNC();
+}
+template <int T, typename F>
+__device__ void forward_block(const WalkerDesc &w, int k, uint32_t sweep, Lds &L, F *const phi[2], bool resident,
+                              int mm, ChainAcc &acc) {
+  forward_block_body<T, F>(w, k, sweep, L, phi, resident, mm, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -2360,7 +2386,7 @@ __device__ double right_stack(const WalkerDesc &w, int sp, Lds &L, double *Phi) 
 }
 
 // M = P^T Q_n and its inverse into Minv (global); returns log|det M|, sign.
-__device__ void inverse_at_beta(const WalkerDesc &w, int sp, Lds &L, double *logabs, int *sign) {
+__device__ __noinline__ void inverse_at_beta(const WalkerDesc &w, int sp, Lds &L, double *logabs, int *sign) {
   const int m = w.ne[sp], N = w.N;
   const double *Qn = w.RQ[sp] + (size_t)(w.nblk - 1) * N * m;
   for (int t = TID; t < m * m; t += kThreads) {
@@ -2494,7 +2520,7 @@ __device__ __forceinline__ void forward_walker(const WalkerDesc &w, Lds &L, cons
     sc->fock_logw[0] = sc->fock_logw[1] = 0.0;
     sc->fock_sign[0] = sc->fock_sign[1] = 1;
   }
-  ChainAcc acc{0.0, 1.0, 0, 0};
+  ChainAcc acc{0.0, 1.0, 0, 0, 0};
   for (int sp = 0; sp < 2; ++sp) fill_P(w, sp, phi[sp]);
   double ld_tot = 0.0;
   for (int k = 1; k <= n; ++k) {
@@ -2509,7 +2535,10 @@ __device__ __forceinline__ void forward_walker(const WalkerDesc &w, Lds &L, cons
       if (m > 0 && !gj_inverse(L.A, sp ? L.Ms1 : L.Ms0, m, L, &la, &sg))
         if (TID == 0) w.sc->status |= 4;
     }
-    forward_block<TSEL, F>(w, k, sweep, L, phi, resident, xld, acc);
+    // the Ne <= 8 chain (short per-site steps) runs in the kernel's own
+    // frame; the longer chains are calls
+    if constexpr (TSEL == 1) forward_block_body<1, F>(w, k, sweep, L, phi, resident, xld, acc);
+    else forward_block<TSEL, F>(w, k, sweep, L, phi, resident, xld, acc);
     // block end: diagonal of A from the updated inverse, kept for the wrap check
     if (k < n && want_aw)
       for (int sp = 0; sp < 2; ++sp) {
@@ -2555,6 +2584,7 @@ __device__ __forceinline__ void forward_walker(const WalkerDesc &w, Lds &L, cons
     sc->fresh_sign = sg_tot;
     if (!(w.flags & 2)) sc->flip_att += (long long)w.N * w.L;
     sc->flip_acc += acc.nacc;
+    sc->near_ties += acc.nnear;
     sc->sweep = sweep;
   }
 }
@@ -3670,10 +3700,12 @@ __global__ void __launch_bounds__(kThreads) k_fock(const WalkerDesc *__restrict_
     const int jn = pick(uniform01(w.seed, w.wid, kSwapJ, sweep, (uint32_t)sp, (uint32_t)t), w.N - ne);
     const int j = nth_empty(w, sp, jn, L);
     const double xacc = uniform01(w.seed, w.wid, kSwapAcc, sweep, (uint32_t)sp, (uint32_t)t);
-    const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, fw, nullptr);
+    double rr = 0.0;
+    const bool acc = j >= 0 && swap_move(w, sp, k, j, xacc, true, L, fw, &rr);
     if (TID == 0) {
       w.sc->swap_att[sp] += 1;
       if (acc) w.sc->swap_acc[sp] += 1;
+      if (rr != 0.0) w.sc->swap_near[sp] += near_tie_lane(xacc, fabs(rr));
     }
     SYNC();
   }

@@ -65,7 +65,7 @@ class SweepStats(C.Structure):
     _fields_ = [("flip_attempts", C.c_int64), ("flip_accepts", C.c_int64),
                 ("swap_attempts", C.c_int64), ("swap_accepts", C.c_int64),
                 ("max_wrap_err", C.c_double), ("logw_drift", C.c_double),
-                ("qr_shifted", C.c_int64), ("sweeps", C.c_uint64)]
+                ("qr_shifted", C.c_int64), ("sweeps", C.c_uint64), ("near_ties", C.c_int64)]
 
 
 _lib = None

@@ -48,7 +48,7 @@ def test_flat_band_half_filled_sweep(lq):
     lo, soo = o.tracked_weight()
     assert sgg == soo and _close(lg, lo)
     stg, sto = g.stats(), o.stats()
-    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts"):
+    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts", "near_ties"):
         assert stg[k] == sto[k], k
     assert stg["logw_drift"] < 1e-8
     ctx.close()

@@ -55,7 +55,7 @@ def _matches_oracle(g, o):
     lo, soo = o.tracked_weight()
     assert sgg == soo and _close(lg, lo)
     stg, sto = g.stats(), o.stats()
-    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts"):
+    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts", "near_ties"):
         assert stg[k] == sto[k], k
     assert stg["logw_drift"] < 1e-8
     mg, mo = g.measure(), o.measure()

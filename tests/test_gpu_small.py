@@ -41,7 +41,7 @@ def test_small_config_200_sweeps_follow_the_oracle(lq):
     lo, soo = o.tracked_weight()
     assert sgg == soo and abs(lg - lo) <= 1e-10 * max(1.0, abs(lo))
     stg, sto = g.stats(), o.stats()
-    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts"):
+    for k in ("flip_attempts", "flip_accepts", "swap_attempts", "swap_accepts", "near_ties"):
         assert stg[k] == sto[k], k
     mg, mo = g.measure(), o.measure()
     assert mg[1] == mo[1] == 200 * 3          # three interior boundaries per sweep
