@@ -1100,6 +1100,60 @@ __device__ __forceinline__ double div_nr(double d, double r) {
   return d * y;
 }
 
+// Row slots of the register tile.  The 2T rows of a lane's tile sit in its
+// registers in a lane-dependent order: slot s holds row s ^ key of the
+// lane's row group, key depending on the column-group bits (b0, b1, b2) of
+// the lane.  With that order the sums of u = M^{-1} x over the eight lanes of
+// a column group are taken as a reduce-scatter (row_half_mirror, then the
+// quad exchanges xor 1 and xor 2, each step halving the rows a lane carries,
+// so that every partner holds in its sent slots the rows the lane keeps) and
+// the full vector u comes back by the mirrored all-gather, instead of a full
+// butterfly per row.  T = 4: 8 rows, key = (2 b0 + b1) ^ 7 b2; T = 2: 4 rows,
+// key = b0 ^ 3 b2 (lanes that differ in b1 share their row).  T = 1 keeps
+// the row order and the full butterflies: for two rows per lane the
+// reduce-scatter saves no instruction.
+template <int T>
+__device__ __forceinline__ int tile_key(int bc) {
+  const int b0 = bc & 1, b1 = (bc >> 1) & 1, b2 = (bc >> 2) & 1;
+  (void)b1;
+  if constexpr (T == 4) return (2 * b0 + b1) ^ (b2 ? 7 : 0);
+  else if constexpr (T == 2) return b0 ^ (b2 ? 3 : 0);
+  else return 0;
+}
+// u of the lane's 2T row slots from the partial sums t over its T columns,
+// and the lane's share of p . u: each row's partial of a = sum_rows p u is
+// counted by exactly one lane of the column group
+template <int T>
+__device__ __forceinline__ double tile_u(double (&t)[2 * T], const double (&pv)[2 * T], int bc, double (&u)[2 * T]) {
+  if constexpr (T == 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] += dpp_d<0x141>(t[4 + k]);   // row_half_mirror
+#pragma unroll
+    for (int k = 0; k < 2; ++k) t[k] += dpp_d<0xB1>(t[2 + k]);    // quad_perm [1,0,3,2]
+    t[0] += dpp_d<0x4E>(t[1]);                                      // quad_perm [2,3,0,1]
+    u[0] = t[0];
+    u[1] = dpp_d<0x4E>(u[0]);
+    u[2] = dpp_d<0xB1>(u[0]);
+    u[3] = dpp_d<0xB1>(u[1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[4 + k] = dpp_d<0x141>(u[k]);
+    return pv[0] * t[0];
+  } else if constexpr (T == 2) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) t[k] += dpp_d<0x141>(t[2 + k]);
+    t[0] += dpp_d<0xB1>(t[1]);
+    t[0] += dpp_d<0x4E>(t[0]);
+    u[0] = t[0];
+    u[1] = dpp_d<0xB1>(u[0]);
+    u[2] = dpp_d<0x141>(u[0]);
+    u[3] = dpp_d<0x141>(u[1]);
+    return (bc & 2) ? 0.0 : pv[0] * t[0];
+  } else {
+    static_assert(T == 4 || T == 2, "tile_u serves T = 2 and 4");
+    return 0.0;
+  }
+}
+
 // Accepted flips of a chunk are returned as a bit mask (bit r = row r of the
 // chunk); the field flip and the row scaling Phi_R[i,:] *= 1 + Delta are
 // applied by flush_chunk, since no later site of the slice reads them.
@@ -1108,7 +1162,7 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
                                     const PE *prow_g, int ldp, const double *usb_g, const double *dsb_g, int cnt,
                                     int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
-  const int m = w.ne[sp];
+  const int m = w.ne[sp], key = tile_key<T>(bc);
   const lds_f64 *xsp = as_lds(xsb_g) + sp * S * mm + bc * T;
   const lds_f64 *usb = as_lds(usb_g);
   const lds_f64 *dsb = as_lds(dsb_g) + sp * S;
@@ -1117,7 +1171,7 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
   decltype(as_lds(prow_g)) prow[2 * T];
 #pragma unroll
   for (int i = 0; i < 2 * T; ++i) {
-    const int a = ar * 2 * T + i;
+    const int a = ar * 2 * T + (i ^ key);
     prow[i] = as_lds(prow_g) + (a < m ? a : 0);
   }
   struct Row {
@@ -1134,17 +1188,25 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
   unsigned mask = 0;
   auto step = [&](int r, const Row &R) {
     const double delta = R.d;
-    double u[2 * T];
-    double ap = 0.0;
+    double u[2 * T], t[2 * T];
 #pragma unroll
     for (int i = 0; i < 2 * T; ++i) {
-      double t = M[i][0] * R.x[0];
+      t[i] = M[i][0] * R.x[0];
 #pragma unroll
-      for (int j = 1; j < T; ++j) t = fma(M[i][j], R.x[j], t);
-      u[i] = sum_bc(t);
-      ap = fma(R.p[i], u[i], ap);
+      for (int j = 1; j < T; ++j) t[i] = fma(M[i][j], R.x[j], t[i]);
     }
-    const double a = sum_ar(ap);
+    double a;
+    if constexpr (T == 1) {
+      double ap = 0.0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        u[i] = sum_bc(t[i]);
+        ap = fma(R.p[i], u[i], ap);
+      }
+      a = sum_ar(ap);
+    } else {
+      a = sum_ar(sum_bc(tile_u<T>(t, R.p, bc, u)));
+    }
     double wv[T];
 #pragma unroll
     for (int j = 0; j < T; ++j) {
@@ -2051,11 +2113,12 @@ __device__ __forceinline__ void forward_block_body(const WalkerDesc &w, int k, u
     if (TID < 64) {
       const int m = w.ne[sp];
       const double *Ms = sp ? L.Ms1 : L.Ms0;
+      const int key = tile_key<TT>(bc);
 #pragma unroll
       for (int i = 0; i < 2 * T; ++i)
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          const int a = ar * 2 * T + i, b = bc * T + j;
+          const int a = ar * 2 * T + (i ^ key), b = bc * T + j;
           M[i][j] = (a < m && b < m) ? Ms[a * m + b] : 0.0;
         }
     }
@@ -2186,11 +2249,12 @@ __device__ __forceinline__ void forward_block_body(const WalkerDesc &w, int k, u
     if (TID < 64) {
       const int m = w.ne[sp];
       double *Ms = sp ? L.Ms1 : L.Ms0;
+      const int key = tile_key<TT>(bc);
 #pragma unroll
       for (int i = 0; i < 2 * T; ++i)
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          const int a = ar * 2 * T + i, b = bc * T + j;
+          const int a = ar * 2 * T + (i ^ key), b = bc * T + j;
           if (a < m && b < m) Ms[a * m + b] = M[i][j];
         }
     }
