@@ -1153,6 +1153,43 @@ __device__ __forceinline__ double tile_u(double (&t)[2 * T], const double (&pv)[
     return 0.0;
   }
 }
+// Column slots likewise: slot c of a lane holds column c ^ ckey of its column
+// group, ckey depending on the lowest row-group bit a0 (lane bit 3), so that
+// the sums of w = p M^{-1} over the four row groups start with a
+// reduce-scatter over a0 (row_ror:8), take the sum over the other row-group
+// bit on the half as many values (permlane16 pairs) and end with the
+// all-gather over a0.  T = 4: ckey = 2 a0; T = 2: ckey = a0; T = 1: none.
+template <int T>
+__device__ __forceinline__ int tile_ckey(int ar) {
+  if constexpr (T == 4) return 2 * (ar & 1);
+  else if constexpr (T == 2) return ar & 1;
+  else return 0;
+}
+// sum of a value over the two 16-lane rows of each 32-lane half, the same
+// bits in every lane (the second step of sum_ar)
+__device__ __forceinline__ double sum_r16(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+template <int T>
+__device__ __forceinline__ void tile_w(double (&t)[T], double (&wv)[T]) {
+  if constexpr (T == 4) {
+    t[0] += dpp_d<0x128>(t[2]);   // row_ror:8
+    t[1] += dpp_d<0x128>(t[3]);
+    wv[0] = sum_r16(t[0]);
+    wv[1] = sum_r16(t[1]);
+    wv[2] = dpp_d<0x128>(wv[0]);
+    wv[3] = dpp_d<0x128>(wv[1]);
+  } else if constexpr (T == 2) {
+    t[0] += dpp_d<0x128>(t[1]);
+    wv[0] = sum_r16(t[0]);
+    wv[1] = dpp_d<0x128>(wv[0]);
+  } else {
+    wv[0] = sum_ar(t[0]);
+  }
+}
 
 // Accepted flips of a chunk are returned as a bit mask (bit r = row r of the
 // chunk); the field flip and the row scaling Phi_R[i,:] *= 1 + Delta are
@@ -1162,7 +1199,7 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
                                     const PE *prow_g, int ldp, const double *usb_g, const double *dsb_g, int cnt,
                                     int S, ChainAcc &acc) {
   const int lane = TID & 63, sp = lane >> 5, h = lane & 31, ar = h >> 3, bc = h & 7;
-  const int m = w.ne[sp], key = tile_key<T>(bc);
+  const int m = w.ne[sp], key = tile_key<T>(bc), ckey = tile_ckey<T>(ar);
   const lds_f64 *xsp = as_lds(xsb_g) + sp * S * mm + bc * T;
   const lds_f64 *usb = as_lds(usb_g);
   const lds_f64 *dsb = as_lds(dsb_g) + sp * S;
@@ -1179,7 +1216,7 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
   };
   auto load = [&](int r, Row &R) {
 #pragma unroll
-    for (int j = 0; j < T; ++j) R.x[j] = xsp[r * mm + j];
+    for (int j = 0; j < T; ++j) R.x[j] = xsp[r * mm + (j ^ ckey)];
 #pragma unroll
     for (int i = 0; i < 2 * T; ++i) R.p[i] = (double)prow[i][r * ldp];
     R.d = dsb[r];
@@ -1207,14 +1244,14 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
     } else {
       a = sum_ar(sum_bc(tile_u<T>(t, R.p, bc, u)));
     }
-    double wv[T];
+    double wv[T], tw[T];
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-      double t = R.p[0] * M[0][j];
+      tw[j] = R.p[0] * M[0][j];
 #pragma unroll
-      for (int i = 1; i < 2 * T; ++i) t = fma(R.p[i], M[i][j], t);
-      wv[j] = sum_ar(t);
+      for (int i = 1; i < 2 * T; ++i) tw[j] = fma(R.p[i], M[i][j], tw[j]);
     }
+    tile_w<T>(tw, wv);
     const double rsp = fma(delta, a, 1.0);
     const double ratio = halves_product(rsp);
     acc.nnear += near_tie(R.u, fabs(ratio));
@@ -2113,12 +2150,12 @@ __device__ __forceinline__ void forward_block_body(const WalkerDesc &w, int k, u
     if (TID < 64) {
       const int m = w.ne[sp];
       const double *Ms = sp ? L.Ms1 : L.Ms0;
-      const int key = tile_key<TT>(bc);
+      const int key = tile_key<TT>(bc), ckey = tile_ckey<TT>(ar);
 #pragma unroll
       for (int i = 0; i < 2 * T; ++i)
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          const int a = ar * 2 * T + (i ^ key), b = bc * T + j;
+          const int a = ar * 2 * T + (i ^ key), b = bc * T + (j ^ ckey);
           M[i][j] = (a < m && b < m) ? Ms[a * m + b] : 0.0;
         }
     }
@@ -2249,12 +2286,12 @@ __device__ __forceinline__ void forward_block_body(const WalkerDesc &w, int k, u
     if (TID < 64) {
       const int m = w.ne[sp];
       double *Ms = sp ? L.Ms1 : L.Ms0;
-      const int key = tile_key<TT>(bc);
+      const int key = tile_key<TT>(bc), ckey = tile_ckey<TT>(ar);
 #pragma unroll
       for (int i = 0; i < 2 * T; ++i)
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          const int a = ar * 2 * T + (i ^ key), b = bc * T + j;
+          const int a = ar * 2 * T + (i ^ key), b = bc * T + (j ^ ckey);
           if (a < m && b < m) Ms[a * m + b] = M[i][j];
         }
     }
