@@ -1059,7 +1059,8 @@ __device__ __forceinline__ double lane_read(double v, int lane) {
 // auxiliary-field sweep, as in projector QMC).
 //
 // Register-tiled version for Ne <= 8T: lane (ar, bc) of a half holds rows
-// ar*2T .. ar*2T+2T-1 and columns bc*T .. bc*T+T-1 of its spin's inverse.
+// ar*2T .. ar*2T+2T-1 and columns bc*T .. bc*T+T-1 of its spin's inverse,
+// in the lane-dependent slot order of tile_key / tile_ckey below.
 // ---------------------------------------------------------------------------
 // log|W| bookkeeping of accepted flips: a mantissa product renormalised by
 // exponent bits (exact power-of-two scaling), logged once per block.
@@ -1232,6 +1233,14 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
 #pragma unroll
       for (int j = 1; j < T; ++j) t[i] = fma(M[i][j], R.x[j], t[i]);
     }
+    double wv[T], tw[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      tw[j] = R.p[0] * M[0][j];
+#pragma unroll
+      for (int i = 1; i < 2 * T; ++i) tw[j] = fma(R.p[i], M[i][j], tw[j]);
+    }
+    tile_w<T>(tw, wv);
     double a;
     if constexpr (T == 1) {
       double ap = 0.0;
@@ -1242,27 +1251,34 @@ __device__ unsigned chain_chunk_reg(const WalkerDesc &w, double (&M)[2 * T][T], 
       }
       a = sum_ar(ap);
     } else {
-      a = sum_ar(sum_bc(tile_u<T>(t, R.p, bc, u)));
-    }
-    double wv[T], tw[T];
+      // u for the update; a = (p M^{-1}) . x over the lane's columns, then
+      // over the column groups (w is the same in the four row groups)
+      tile_u<T>(t, R.p, bc, u);
+      double xa = wv[0] * R.x[0];
 #pragma unroll
-    for (int j = 0; j < T; ++j) {
-      tw[j] = R.p[0] * M[0][j];
-#pragma unroll
-      for (int i = 1; i < 2 * T; ++i) tw[j] = fma(R.p[i], M[i][j], tw[j]);
+      for (int j = 1; j < T; ++j) xa = fma(wv[j], R.x[j], xa);
+      a = sum_bc(xa);
     }
-    tile_w<T>(tw, wv);
     const double rsp = fma(delta, a, 1.0);
     const double ratio = halves_product(rsp);
     acc.nnear += near_tie(R.u, fabs(ratio));
     // ratio and the uniform are identical in every lane: a scalar branch
     if (accept_site(R.u, fabs(ratio))) {
       const double c = div_nr(delta, rsp);
+      if constexpr (T == 1) {
 #pragma unroll
-      for (int i = 0; i < 2 * T; ++i) {
-        const double cu = c * u[i];
+        for (int i = 0; i < 2; ++i) {
+          const double cu = c * u[i];
+          M[i][0] = fma(-cu, wv[0], M[i][0]);
+        }
+      } else {
+        double cw[T];
 #pragma unroll
-        for (int j = 0; j < T; ++j) M[i][j] = fma(-cu, wv[j], M[i][j]);
+        for (int j = 0; j < T; ++j) cw[j] = c * wv[j];
+#pragma unroll
+        for (int i = 0; i < 2 * T; ++i)
+#pragma unroll
+          for (int j = 0; j < T; ++j) M[i][j] = fma(-u[i], cw[j], M[i][j]);
       }
       mask |= 1u << r;
       acc_ratio(acc, fabs(ratio));
