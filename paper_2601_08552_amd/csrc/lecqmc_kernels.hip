@@ -310,15 +310,16 @@ __device__ __forceinline__ void colour_pass_tt(const WalkerDesc &w, const BondSr
   const int per = m > 0 ? kThreads / m : 0;
   const int col = m > 0 ? TID % m : 0, slot = m > 0 ? TID / m : kThreads;
   if (slot < per) {
-    // four bonds per thread per round: all loads first, then all stores (the
+    // eight bonds per thread per round: all loads first, then all stores (the
     // bonds of one colour are disjoint, so nothing aliases).  A slot past the
     // colour's end loads bond b0 again and stores nothing, so that no load
     // waits behind a branch.
-    for (int bb = b0 + slot; bb < b1; bb += 4 * per) {
-      int ii[4], jj[4];
-      E xi[4], xj[4], d[4], o[4];
+    constexpr int kB = 8;
+    for (int bb = b0 + slot; bb < b1; bb += kB * per) {
+      int ii[kB], jj[kB];
+      E xi[kB], xj[kB], d[kB], o[kB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kB; ++u) {
         const int b = bb + u * per < b1 ? bb + u * per : b0;
         int i, j;
         double dd, oo;
@@ -331,7 +332,7 @@ __device__ __forceinline__ void colour_pass_tt(const WalkerDesc &w, const BondSr
         xj[u] = X[jj[u]];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < kB; ++u)
         if (bb + u * per < b1) {
           X[ii[u]] = d[u] * xi[u] + o[u] * xj[u];
           X[jj[u]] = o[u] * xi[u] + d[u] * xj[u];
