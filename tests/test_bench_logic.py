@@ -48,3 +48,13 @@ def test_committed_counter_record_is_well_formed():
               "fetch_scale", "write_scale", "calibration"):
         assert k in rec, k
     assert len(rec["src_sha256"]) == 64 and rec["fetch_kib_per_dispatch"] > 0 and rec["write_kib_per_dispatch"] > 0
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
